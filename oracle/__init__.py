@@ -1,0 +1,326 @@
+"""CPU oracle for the Monte Carlo hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product library never loads it and
+shares no code with it.
+
+The arithmetic lives in ``mcoracle.c`` (plain C, built with gcc, OpenMP over
+independent sites / replicas / walkers); this module only builds it, marshals
+numpy arrays and strings the steps of the population-annealing and
+multicanonical loops together in the order the paper gives them (M. Weigel,
+arXiv:1709.04394, Sec. "Population annealing" and Sec. "Multicanonical
+simulations").  Exact references (enumeration, Kaufman, Onsager, Yang, exact
+density of states) are in ``oracle.exact``; the FP64 MLP is ``oracle.mlp``.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mcoracle.c")
+_LIB = os.path.join(_HERE, "libmcoracle.so")
+
+TAG_INIT, TAG_SWEEP, TAG_COUPLING, TAG_RESAMPLE = 1, 2, 3, 4
+TAG_MUCA, TAG_MLP_INIT, TAG_SWEEP_LO, TAG_MUCA_LO = 5, 6, 7, 8
+METROPOLIS, HEATBATH = 0, 1
+COLD, HOT = 0, 1
+
+
+def build(force: bool = False) -> str:
+    """Compile mcoracle.c with gcc (plain IEEE double, no contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-std=c11",
+               "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        u8p = ctypes.c_void_p
+        L.orc_philox4x32_10.argtypes = [u8p, u8p, u8p]
+        L.orc_draw_byte.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                    ctypes.c_uint64, ctypes.c_uint32]
+        L.orc_draw_byte.restype = ctypes.c_uint32
+        L.orc_draw32.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                 ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32]
+        L.orc_draw32.restype = ctypes.c_uint32
+        L.orc_resample_u.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
+        L.orc_resample_u.restype = ctypes.c_double
+        L.orc_metropolis_table.argtypes = [ctypes.c_double, ctypes.c_int, u8p]
+        L.orc_heatbath_table.argtypes = [ctypes.c_double, ctypes.c_int, u8p]
+        L.orc_init.argtypes = [ctypes.c_int] * 4 + [u8p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32]
+        L.orc_couplings.argtypes = [ctypes.c_int] * 4 + [u8p, ctypes.c_uint64]
+        L.orc_measure.argtypes = [ctypes.c_int] * 4 + [u8p, u8p, u8p, u8p]
+        L.orc_measure.restype = None
+        L.orc_sweep.argtypes = [ctypes.c_int] * 4 + [u8p, u8p, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
+                                                     ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, u8p]
+        L.orc_sweep_q3.argtypes = [ctypes.c_int, u8p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                                   ctypes.c_uint64, ctypes.c_int, u8p]
+        L.orc_canonical_scan.argtypes = [u8p, u8p, ctypes.c_int64]
+        L.orc_canonical_scan.restype = None
+        L.orc_pa_init.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, u8p, u8p]
+        L.orc_pa_steps.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, u8p,
+                                   ctypes.c_int, ctypes.c_uint64, u8p, u8p, u8p, u8p, u8p, u8p]
+        L.orc_muca_table.argtypes = [ctypes.c_int, u8p, u8p]
+        L.orc_muca_table.restype = None
+        L.orc_muca_start.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, u8p, u8p]
+        L.orc_muca_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, u8p, u8p, u8p, ctypes.c_uint64,
+                                      ctypes.c_uint64, ctypes.c_int, ctypes.c_int, u8p]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError("oracle %s rejected its arguments (rc=%d)" % (what, rc))
+
+
+# --------------------------------------------------------------------------- RNG
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def draw_byte(seed, tag, j, replica, sweep, phase):
+    return int(lib().orc_draw_byte(seed, tag, j, replica, sweep, phase))
+
+
+def draw32(seed, tag, tag_lo, j, replica, sweep, phase):
+    return int(lib().orc_draw32(seed, tag, tag_lo, j, replica, sweep, phase))
+
+
+def resample_u(seed, k, pop, step):
+    return float(lib().orc_resample_u(seed, k, pop, step))
+
+
+# ------------------------------------------------------------------------ tables
+def metropolis_table(beta, kmax=3):
+    T = np.zeros(kmax + 1, dtype=np.uint64)
+    lib().orc_metropolis_table(float(beta), kmax, _p(T))
+    return T
+
+
+def heatbath_table(beta, z):
+    T = np.zeros(2 * z + 1, dtype=np.uint64)
+    lib().orc_heatbath_table(float(beta), z, _p(T))
+    return T
+
+
+# ---------------------------------------------------------------------- lattices
+def _shape(dims, L):
+    if isinstance(L, int):
+        L = (L,) * dims
+    Lx, Ly = L[0], L[1]
+    Lz = L[2] if dims == 3 else 1
+    return Lx, Ly, Lz
+
+
+def init(dims, L, start, seed, replica=0):
+    Lx, Ly, Lz = _shape(dims, L)
+    s = np.zeros(Lx * Ly * Lz, dtype=np.int8)
+    _check(lib().orc_init(dims, Lx, Ly, Lz, _p(s), start, seed, replica), "init")
+    return s
+
+
+def couplings(dims, L, seed):
+    Lx, Ly, Lz = _shape(dims, L)
+    J = np.zeros(dims * Lx * Ly * Lz, dtype=np.int8)
+    _check(lib().orc_couplings(dims, Lx, Ly, Lz, _p(J), seed), "couplings")
+    return J
+
+
+def measure(dims, L, s, J=None):
+    Lx, Ly, Lz = _shape(dims, L)
+    E = np.zeros(1, dtype=np.int64)
+    M = np.zeros(1, dtype=np.int64)
+    s = np.ascontiguousarray(s, dtype=np.int8)
+    Jc = None if J is None else np.ascontiguousarray(J, dtype=np.int8)
+    lib().orc_measure(dims, Lx, Ly, Lz, _p(s), _p(Jc), _p(E), _p(M))
+    return int(E[0]), int(M[0])
+
+
+def sweep(dims, L, s, beta, seed, replica, sweep0, nsweeps, rule=METROPOLIS, J=None, record=True):
+    """Run nsweeps checkerboard sweeps in place on int8 lattice s; returns EM [n,2] or None."""
+    Lx, Ly, Lz = _shape(dims, L)
+    assert s.dtype == np.int8 and s.flags.c_contiguous and s.size == Lx * Ly * Lz
+    EM = np.zeros((nsweeps, 2), dtype=np.int64) if record else None
+    Jc = None if J is None else np.ascontiguousarray(J, dtype=np.int8)
+    _check(lib().orc_sweep(dims, Lx, Ly, Lz, _p(s), _p(Jc), rule, float(beta), seed, replica, sweep0,
+                           nsweeps, _p(EM)), "sweep")
+    return EM
+
+
+def sweep_q3(L, s, beta, seed, replica, sweep0, nsweeps, record=True):
+    EM = np.zeros((nsweeps, 2), dtype=np.int64) if record else None
+    _check(lib().orc_sweep_q3(L, _p(s), float(beta), seed, replica, sweep0, nsweeps, _p(EM)), "sweep_q3")
+    return EM
+
+
+# ----------------------------------------------------------- population annealing
+def canonical_scan(w):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    C = np.zeros_like(w)
+    lib().orc_canonical_scan(_p(w), _p(C), w.size)
+    return C
+
+
+def pa_schedule(nsteps, beta_final=1.0):
+    """beta_i = i * beta_final / nsteps (linear annealing from beta_0 = 0)."""
+    return np.array([i * beta_final / nsteps for i in range(nsteps + 1)], dtype=np.float64)
+
+
+class PAPopulation:
+    """One annealing population of R replicas of the L x L ferromagnet."""
+
+    def __init__(self, L, R, pop, seed):
+        self.L, self.R, self.pop, self.seed = L, R, pop, seed
+        self.N = L * L
+        self.spins = np.zeros(R * self.N, dtype=np.int8)
+        self.E = np.zeros(R, dtype=np.int64)
+        _check(lib().orc_pa_init(L, R, pop, seed, _p(self.spins), _p(self.E)), "pa_init")
+        self.step = 0
+        self.lnZ = [self.N * math.log(2.0)]
+        self.lnQ, self.Ctot = [], []
+        h0 = np.zeros(self.N + 1, dtype=np.int64)
+        np.add.at(h0, (self.E + 2 * self.N) // 4, 1)
+        self.hist = [h0]
+        self.last_counts = None
+
+    def advance(self, beta, theta, nsteps):
+        Ct = np.zeros(nsteps, dtype=np.float64)
+        lq = np.zeros(nsteps, dtype=np.float64)
+        hist = np.zeros((nsteps, self.N + 1), dtype=np.int64)
+        counts = np.zeros(self.R, dtype=np.int32)
+        beta = np.ascontiguousarray(beta, dtype=np.float64)
+        _check(lib().orc_pa_steps(self.L, self.R, self.pop, self.step + 1, nsteps, _p(beta), theta, self.seed,
+                                  _p(self.spins), _p(self.E), _p(Ct), _p(lq), _p(hist), _p(counts)), "pa_steps")
+        for s in range(nsteps):
+            self.Ctot.append(float(Ct[s]))
+            self.lnQ.append(float(lq[s]))
+            # ln Z(beta_i) = ln Z(beta_{i-1}) + ln Q_i, ln Z(0) = N ln 2
+            self.lnZ.append(self.lnZ[-1] + float(lq[s]))
+            self.hist.append(hist[s])
+        self.step += nsteps
+        self.last_counts = counts
+        return self
+
+
+def pa_anneal(Ls, R, beta, theta, seed, nsteps=None):
+    """All populations (one per L) from beta_0 = 0 through the whole schedule."""
+    nsteps = len(beta) - 1 if nsteps is None else nsteps
+    pops = []
+    for p, L in enumerate(Ls):
+        pops.append(PAPopulation(L, R, p, seed).advance(beta, theta, nsteps))
+    return pops
+
+
+# -------------------------------------------------------------------- multicanonical
+def muca_levels(L):
+    """Number of levels in the window [-2N, 0]: k = (E + 2N)/4 = 0..N/2."""
+    return L * L // 2 + 1
+
+
+def muca_table(L, lnW):
+    lnW = np.ascontiguousarray(lnW, dtype=np.float64)
+    T = np.zeros((muca_levels(L), 4), dtype=np.uint64)
+    lib().orc_muca_table(L, _p(lnW), _p(T))
+    return T
+
+
+def muca_start(L, walkers, seed):
+    N = L * L
+    spins = np.zeros(walkers * N, dtype=np.int8)
+    E = np.zeros(walkers, dtype=np.int64)
+    _check(lib().orc_muca_start(L, walkers, seed, _p(spins), _p(E)), "muca_start")
+    return spins, E
+
+
+def muca_sweeps(L, spins, E, lnW, seed, sweep0, nsweeps, record):
+    walkers = E.size
+    H = np.zeros(muca_levels(L), dtype=np.int64)
+    lnW = np.ascontiguousarray(lnW, dtype=np.float64)
+    _check(lib().orc_muca_sweeps(L, walkers, _p(spins), _p(E), _p(lnW), seed, sweep0, nsweeps,
+                                 1 if record else 0, _p(H)), "muca_sweeps")
+    return H
+
+
+def muca_flat_levels(L):
+    """Levels of the window that any state can reach: all but k = 1."""
+    K = muca_levels(L)
+    mask = np.ones(K, dtype=bool)
+    mask[1] = False
+    return mask
+
+
+def muca_flatness(L, H):
+    m = muca_flat_levels(L)
+    h = H[m]
+    return float(h.min()) / float(h.max()) if h.max() > 0 else 0.0
+
+
+def muca_update(L, lnW, H):
+    """W^(n+1) = W^(n) / H^(n) (Eq. weight_modification) in logs, where H > 0;
+    then renormalised so that ln W at E = 0 (level N/2) is zero."""
+    out = np.array(lnW, dtype=np.float64)
+    for k in range(out.size):
+        if H[k] > 0:
+            out[k] = out[k] - math.log(float(H[k]))
+    ref = out[-1]
+    for k in range(out.size):
+        out[k] = out[k] - ref
+    return out
+
+
+def muca_run(L, walkers, seed, eq_sweeps, rec_sweeps, max_iter, prod_sweeps, flat=0.8, lnW_init=None):
+    """Parallel-walker multicanonical iteration: every walker shares W; the
+    histograms of all walkers are added; the weights follow the plain recursion
+    until the histogram is flat (min/max over reachable levels >= flat); then a
+    production run at fixed weights gives ln g = ln H - ln W."""
+    K = muca_levels(L)
+    lnW = np.zeros(K) if lnW_init is None else np.array(lnW_init, dtype=np.float64)
+    spins, E = muca_start(L, walkers, seed)
+    sweep = 0
+    it, converged, ratio = 0, False, 0.0
+    history = []
+    while it < max_iter:
+        muca_sweeps(L, spins, E, lnW, seed, sweep, eq_sweeps, False)
+        sweep += eq_sweeps
+        H = muca_sweeps(L, spins, E, lnW, seed, sweep, rec_sweeps, True)
+        sweep += rec_sweeps
+        it += 1
+        ratio = muca_flatness(L, H)
+        history.append(ratio)
+        if ratio >= flat:
+            converged = True
+            break
+        lnW = muca_update(L, lnW, H)
+    Hp = muca_sweeps(L, spins, E, lnW, seed, sweep, prod_sweeps, True) if prod_sweeps > 0 else None
+    lng = None
+    if Hp is not None:
+        lng = np.full(K, -np.inf)
+        for k in range(K):
+            if Hp[k] > 0:
+                lng[k] = math.log(float(Hp[k])) - lnW[k]
+    return dict(lnW=lnW, iterations=it, converged=converged, min_over_max=ratio, sweeps_per_walker=sweep,
+                H_prod=Hp, lng=lng, spins=spins, E=E, history=history)

@@ -1,0 +1,108 @@
+"""Pins of the oracle's random streams (Philox4x32-10, Sec. "Random number
+generation", counter-based generators).
+
+* Known answers: the oracle's Philox block equals rocRAND's host-side
+  Philox4x32-10 engine (an independent implementation shipped with ROCm, built
+  here from its header) for edge and random (key, counter) values.
+* The 32-bit draws assembled from two blocks are uniform (chi-square on the top
+  byte and on the low bits), distinct streams are uncorrelated, and the 53-bit
+  resampling variate lies in [0, 1).
+"""
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _rocrand_blocks(cases):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
+        pytest.skip("rocRAND headers / hipcc not available")
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "kat")
+        subprocess.run([hipcc, "-O1", "-I/opt/rocm/include", os.path.join(HERE, "philox_rocrand_kat.cpp"),
+                        "-o", exe], check=True, capture_output=True)
+        inp = "\n".join(" ".join(str(int(v)) for v in c) for c in cases) + "\n"
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    return [list(map(int, line.split())) for line in out.strip().splitlines()]
+
+
+def test_philox_matches_rocrand():
+    rng = np.random.default_rng(2024)
+    # rocRAND reaches counter word x1 through a 64-bit offset of 4 (x0 + 2^32 x1)
+    # numbers, so its mapping covers x1 < 2^30; x1 stays in that range here.
+    top = 0xFFFFFFFF
+    cases = [(0, 0, 0, 0, 0, 0), (top, top, top, 0x3FFFFFFF, top, top), (1, 0, 0, 0, 0, 0),
+             (0, 0, 1, 0, 0, 0), (0, 0, 0, 0, 0, 0x80000000), (7, 0, 123456, 3, 9999, (2 << 24) | (1 << 23))]
+    for _ in range(24):
+        v = [int(x) for x in rng.integers(0, 2 ** 32, size=6, dtype=np.uint64)]
+        v[3] >>= 2
+        cases.append(tuple(v))
+    ref = _rocrand_blocks(cases)
+    for c, r in zip(cases, ref):
+        got = oracle.philox([c[2], c[3], c[4], c[5]], [c[0], c[1]])
+        assert [int(v) for v in got] == r, c
+
+
+def test_philox_counter_sensitivity():
+    # every counter word and key word changes every output word (avalanche)
+    base = oracle.philox([1, 2, 3, 4], [5, 6])
+    for pos in range(6):
+        ctr, key = [1, 2, 3, 4], [5, 6]
+        if pos < 4:
+            ctr[pos] ^= 1
+        else:
+            key[pos - 4] ^= 1
+        other = oracle.philox(ctr, key)
+        assert np.all(other != base)
+
+
+def _chi2(counts, expected):
+    return float(((counts - expected) ** 2 / expected).sum())
+
+
+def test_draw32_uniform_bytes_and_bits():
+    n = 40000
+    r = np.array([oracle.draw32(99, oracle.TAG_SWEEP, oracle.TAG_SWEEP_LO, j, 3, 17, 1) for j in range(n)],
+                 dtype=np.uint64)
+    top = np.bincount((r >> 24).astype(np.int64), minlength=256)
+    # 255 dof: mean 255, sd ~22.6; 6 sd bound
+    assert _chi2(top, n / 256) < 255 + 6 * 22.6
+    low = np.bincount((r & 0xFF).astype(np.int64), minlength=256)
+    assert _chi2(low, n / 256) < 255 + 6 * 22.6
+    bits = np.array([((r >> b) & 1).mean() for b in range(32)])
+    assert np.all(np.abs(bits - 0.5) < 6 * 0.5 / np.sqrt(n))
+
+
+def test_draw_streams_distinct():
+    # neighbouring replicas / sweeps / phases / tags give unrelated streams
+    ref = np.array([oracle.draw32(5, 2, 7, j, 0, 0, 0) for j in range(2000)], dtype=np.float64)
+    for args in [(5, 2, 7, None, 1, 0, 0), (5, 2, 7, None, 0, 1, 0), (5, 2, 7, None, 0, 0, 1),
+                 (6, 2, 7, None, 0, 0, 0), (5, 5, 8, None, 0, 0, 0), (5, 2, 7, None, 0, 1 << 32, 0)]:
+        other = np.array([oracle.draw32(args[0], args[1], args[2], j, args[4], args[5], args[6])
+                          for j in range(2000)], dtype=np.float64)
+        assert np.mean(ref == other) < 0.01
+        c = np.corrcoef(ref, other)[0, 1]
+        assert abs(c) < 6 / np.sqrt(2000)
+
+
+def test_draw_byte_is_top_byte_of_draw32():
+    for j in range(300):
+        b = oracle.draw_byte(11, oracle.TAG_SWEEP, j, 4, 8, 1)
+        r = oracle.draw32(11, oracle.TAG_SWEEP, oracle.TAG_SWEEP_LO, j, 4, 8, 1)
+        assert r >> 24 == b
+
+
+def test_resample_u_range_and_mean():
+    u = np.array([oracle.resample_u(17, k, 2, 33) for k in range(20000)])
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert abs(u.mean() - 0.5) < 6 * np.sqrt(1 / 12 / u.size)
+    # 53-bit grid
+    assert np.all(u * 2.0 ** 53 == np.floor(u * 2.0 ** 53))
