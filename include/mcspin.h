@@ -1,0 +1,139 @@
+/*
+ * mcspin.h -- C ABI of libmcspin, a gfx950 (MI355X) Monte Carlo engine for
+ * Ising-type lattice spin models.
+ *
+ * Method: M. Weigel, "Monte Carlo methods for massively parallel computers",
+ * arXiv:1709.04394.  Section names below refer to that text.
+ *
+ * Conventions shared by every call
+ *   - Plain C types only.  A `stream` argument is a hipStream_t passed as
+ *     void* (NULL = the default stream).  Pointers documented as "device" must
+ *     point to memory of the context's device; "host" pointers to host memory.
+ *   - The caller owns every buffer.  The library never allocates or frees
+ *     device memory inside a call; scratch space comes from caller workspaces
+ *     whose size the matching *_workspace_bytes() call reports.
+ *   - Return value: 0 on success, a negative mc_status otherwise.  Arguments
+ *     are checked in full before any device work is enqueued, so a failing call
+ *     has no side effect.  mc_strerror() names a code, mc_ctx_last_error() gives
+ *     the detail of the last failure on a context.  No C++ exception crosses
+ *     this boundary.  Use one context per host thread.
+ *   - Stream-ordered calls (mc_init, mc_couplings, mc_sweep, mc_measure,
+ *     mc_muca_sweeps, mc_mlp_*) return once their work is enqueued; device
+ *     buffers must stay alive until the stream has passed the call.  Calls that
+ *     return host results (mc_pa_anneal, mc_muca_run) synchronise the stream.
+ *   - Determinism: every output is a pure function of the inputs, the seed and
+ *     the sweep numbers.  It does not depend on launch shape, tile choice, the
+ *     number of lattices per launch or the run (Sec. "Random number
+ *     generation": counter-based generators keyed by intrinsic variables).
+ *
+ * Lattice layout (MC_INT8): spins[l][z][y][x], x fastest, one int8 per site,
+ * values +1 / -1; l = 0..count-1 are independent lattices whose random
+ * streams use replica ids replica0 + l.  MC_MSC64 (multi-spin coding, Sec.
+ * "Checkerboard scheme"): words[l][z][y][x] of uint64, bit b of a word is the
+ * spin of replica replica0 + 64 l + b at that site, bit set <=> s = -1.
+ * Couplings (+-J model, Sec. "Disordered systems"): J[d][z][y][x] int8 +-1 is
+ * the coupling of the bond (site, site + e_d), d = x, y(, z); NULL means J = 1.
+ * Boundary conditions are periodic in every direction.
+ */
+#ifndef MCSPIN_H
+#define MCSPIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MC_ABI_VERSION 1
+
+typedef struct mc_ctx mc_ctx;
+
+typedef enum {
+    MC_OK = 0,
+    MC_E_INVAL = -1,     /* null pointer, unknown enum value                     */
+    MC_E_SHAPE = -2,     /* odd or too small extent, unsupported shape             */
+    MC_E_RANGE = -3,     /* beta < 0 or NaN, negative counts, sizes out of range   */
+    MC_E_LAYOUT = -4,    /* layout / rule / coupling combination not supported     */
+    MC_E_WORKSPACE = -5, /* workspace missing or smaller than required             */
+    MC_E_DEVICE = -6,    /* HIP runtime error (detail in mc_ctx_last_error)        */
+    MC_E_NOTCONV = -7    /* multicanonical run hit max_iter (outputs still valid)  */
+} mc_status;
+
+enum { MC_INT8 = 0, MC_MSC64 = 1 };
+enum { MC_METROPOLIS = 0, MC_HEATBATH = 1 };
+enum { MC_COLD = 0, MC_HOT = 1 };
+
+/* dims = 2 or 3; Lz = 1 when dims == 2; count = number of int8 lattices or of
+ * 64-lane word lattices.  Every extent must be even and >= 4.              */
+typedef struct {
+    int32_t dims, Lx, Ly, Lz, layout, count;
+} mc_geom;
+
+typedef struct {
+    int32_t rule;      /* MC_METROPOLIS or MC_HEATBATH                          */
+    double beta;       /* inverse temperature, >= 0                             */
+    uint64_t seed;     /* Philox key                                            */
+    uint32_t replica0; /* replica id of lattice 0 (of lane 0 for MC_MSC64)      */
+    uint64_t sweep0;   /* global number of the first sweep of this call         */
+    int32_t nsweeps;   /* >= 0                                                  */
+} mc_sweep_args;
+
+int mc_abi_version(void);
+const char *mc_strerror(int code);
+
+/* Create a context bound to HIP device `device` (host state only; the device
+ * is first used, and checked, by the first call that enqueues work). */
+int mc_ctx_create(mc_ctx **out, int device);
+void mc_ctx_destroy(mc_ctx *ctx);
+const char *mc_ctx_last_error(const mc_ctx *ctx);
+
+/* Lattice initialisation (Sec. "Checkerboard scheme", step 1).
+ * MC_COLD: every spin +1.  MC_HOT: site i of replica r is +1 iff byte (i mod
+ * 16) of Philox4x32-10(key = seed, ctr = (i/16, r, 0, TAG_INIT << 24)) is
+ * below 128, i.e. an independent fair coin per site.
+ * spins: device, layout per geom.  Stream-ordered.                         */
+int mc_init(mc_ctx *ctx, const mc_geom *geom, void *spins, int32_t start, uint64_t seed,
+            uint32_t replica0, void *stream);
+
+/* Bimodal couplings J = +-1 with p = 1/2 (Sec. "Disordered systems"): the
+ * coupling with flat index b = d N + i is +1 iff byte (b mod 16) of
+ * Philox(ctr = (b/16, 0, 0, TAG_COUPLING << 24)) is below 128.
+ * J: device int8 [dims][N] (geom->count is ignored).  Stream-ordered.       */
+int mc_couplings(mc_ctx *ctx, const mc_geom *geom, int8_t *J, uint64_t seed, void *stream);
+
+/* Bytes of scratch mc_sweep can use to run each sweep as one fused launch
+ * (read one buffer, write the other).  With a smaller or NULL workspace
+ * mc_sweep runs the two half-sweeps as two in-place launches; the results
+ * are identical either way.                                                 */
+size_t mc_sweep_workspace_bytes(const mc_geom *geom);
+
+/* nsweeps checkerboard sweeps (Sec. "Checkerboard scheme"): one sweep updates
+ * every site with x+y(+z) even, then every odd site; within a half-sweep all
+ * sites of that colour are updated from the same neighbour values.
+ *   Metropolis (Eq. metropolis-canonical): dE = 2 s_i h_i with
+ *     h_i = sum_j J_ij s_j; flip iff dE <= 0 or r32 < ceil(exp(-beta dE) 2^32).
+ *   Heat-bath (Eq. heatbath): s_i' = +1 iff r32 < ceil(2^32 / (1 + exp(-2 beta h_i))).
+ *   r32 for the site with same-colour index j = i >> 1 of colour c in sweep t
+ *   of replica r: (byte (j mod 16) of Philox(ctr = (j/16, r, t, TAG_SWEEP<<24 |
+ *   c<<23 | t>>32)) << 24) | (word 0 of Philox(ctr = (j, r, t, TAG_SWEEP_LO<<24
+ *   | c<<23 | t>>32)) & 0xFFFFFF).  Tables are built once per call in FP64 on
+ *   the host; the device compares integers only.
+ * spins: device, in/out.  J: device int8 [dims][N] or NULL.
+ * EM: device int64 [nsweeps][count * lanes][2] = (E, M) after each sweep,
+ *     lanes = 1 (MC_INT8) or 64 (MC_MSC64), E = -sum_<ij> J_ij s_i s_j over
+ *     bonds (Eq. ising_model, h = 0), M = sum_i s_i; or NULL.
+ * ws: device scratch of ws_bytes (may be NULL, see above).  Stream-ordered.  */
+int mc_sweep(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *J, const mc_sweep_args *args,
+             int64_t *EM, void *ws, size_t ws_bytes, void *stream);
+
+/* E and M of every lattice (lane) as in mc_sweep; EM: device int64
+ * [count * lanes][2].  Stream-ordered.                                      */
+int mc_measure(mc_ctx *ctx, const mc_geom *geom, const void *spins, const int8_t *J, int64_t *EM,
+               void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCSPIN_H */

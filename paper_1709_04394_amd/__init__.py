@@ -1,0 +1,171 @@
+"""libmcspin: MI355X (gfx950) Monte Carlo engine for Ising-type spin models.
+
+This module is the Python binding of the C ABI in ``include/mcspin.h``.  It
+only marshals arguments: PyTorch provides device memory and the current HIP
+stream, and every step of the method runs in the library's HIP kernels.  If
+``libmcspin.so`` has not been built the import fails loudly; there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmcspin.so")
+
+INT8, MSC64 = 0, 1
+METROPOLIS, HEATBATH = 0, 1
+COLD, HOT = 0, 1
+
+MC_OK, MC_E_INVAL, MC_E_SHAPE, MC_E_RANGE, MC_E_LAYOUT, MC_E_WORKSPACE, MC_E_DEVICE, MC_E_NOTCONV = \
+    0, -1, -2, -3, -4, -5, -6, -7
+
+
+class MCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libmcspin error %d: %s" % (code, msg))
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libmcspin.so is not built (expected at %s); run "
+                      "`python -m paper_1709_04394_amd.build` or __graft_entry__.build()" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp = ctypes.c_void_p
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32), ("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32),
+                ("Lz", ctypes.c_int32), ("layout", ctypes.c_int32), ("count", ctypes.c_int32)]
+
+    @property
+    def N(self):
+        return self.Lx * self.Ly * (self.Lz if self.dims == 3 else 1)
+
+    @property
+    def lanes(self):
+        return 64 if self.layout == MSC64 else 1
+
+
+class SweepArgs(ctypes.Structure):
+    _fields_ = [("rule", ctypes.c_int32), ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("replica0", ctypes.c_uint32), ("sweep0", ctypes.c_uint64), ("nsweeps", ctypes.c_int32)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_c = ctypes
+_lib_fns = dict(
+    mc_abi_version=_sig("mc_abi_version", _c.c_int, []),
+    mc_strerror=_sig("mc_strerror", _c.c_char_p, [_c.c_int]),
+    mc_ctx_create=_sig("mc_ctx_create", _c.c_int, [_c.POINTER(_vp), _c.c_int]),
+    mc_ctx_destroy=_sig("mc_ctx_destroy", None, [_vp]),
+    mc_ctx_last_error=_sig("mc_ctx_last_error", _c.c_char_p, [_vp]),
+    mc_init=_sig("mc_init", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _c.c_int32, _c.c_uint64, _c.c_uint32, _vp]),
+    mc_couplings=_sig("mc_couplings", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _c.c_uint64, _vp]),
+    mc_sweep_workspace_bytes=_sig("mc_sweep_workspace_bytes", _c.c_size_t, [_c.POINTER(Geom)]),
+    mc_sweep=_sig("mc_sweep", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _c.POINTER(SweepArgs), _vp, _vp,
+                                         _c.c_size_t, _vp]),
+    mc_measure=_sig("mc_measure", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _vp, _vp]),
+)
+
+
+def exported_symbols():
+    return sorted(_lib_fns)
+
+
+def abi_version():
+    return _lib.mc_abi_version()
+
+
+def strerror(code):
+    return _lib.mc_strerror(code).decode()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch.Tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return _vp(t.data_ptr())
+
+
+def _stream(device):
+    return _vp(torch.cuda.current_stream(device).cuda_stream)
+
+
+def make_geom(dims, L, layout=INT8, count=1):
+    if isinstance(L, int):
+        L = (L,) * dims
+    Lz = L[2] if dims == 3 else 1
+    return Geom(dims, L[0], L[1], Lz, layout, count)
+
+
+def lattice_tensor(geom, device="cuda"):
+    """Uninitialised lattice buffer of the geometry: int8 [count, N] or the
+    MSC64 words as int64 [count, N] (bit-identical to uint64)."""
+    dt = torch.int8 if geom.layout == INT8 else torch.int64
+    return torch.empty((geom.count, geom.N), dtype=dt, device=device)
+
+
+class Context:
+    """A libmcspin context bound to one HIP device (host state only)."""
+
+    def __init__(self, device=0):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        h = _vp()
+        rc = _lib.mc_ctx_create(ctypes.byref(h), self.device.index or 0)
+        if rc != MC_OK:
+            raise MCError(rc, "mc_ctx_create(device=%s): %s" % (device, strerror(rc)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.mc_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != MC_OK:
+            detail = _lib.mc_ctx_last_error(self._h)
+            raise MCError(rc, "%s: %s (%s)" % (what, strerror(rc), detail.decode() if detail else ""))
+        return rc
+
+    # -------------------------------------------------------------- lattices
+    def init(self, geom, spins, start, seed, replica0=0):
+        return self._check(_lib.mc_init(self._h, ctypes.byref(geom), _ptr(spins), start, seed, replica0,
+                                        _stream(self.device)), "mc_init")
+
+    def couplings(self, geom, J, seed):
+        return self._check(_lib.mc_couplings(self._h, ctypes.byref(geom), _ptr(J), seed, _stream(self.device)),
+                           "mc_couplings")
+
+    def sweep_workspace_bytes(self, geom):
+        return int(_lib.mc_sweep_workspace_bytes(ctypes.byref(geom)))
+
+    def sweep(self, geom, spins, beta, seed, nsweeps, sweep0=0, replica0=0, rule=METROPOLIS, J=None, EM=None,
+              ws=None):
+        a = SweepArgs(rule, float(beta), seed, replica0, sweep0, nsweeps)
+        wsb = 0 if ws is None else ws.numel() * ws.element_size()
+        return self._check(_lib.mc_sweep(self._h, ctypes.byref(geom), _ptr(spins), _ptr(J), ctypes.byref(a),
+                                         _ptr(EM), _ptr(ws), wsb, _stream(self.device)), "mc_sweep")
+
+    def measure(self, geom, spins, EM, J=None):
+        return self._check(_lib.mc_measure(self._h, ctypes.byref(geom), _ptr(spins), _ptr(J), _ptr(EM),
+                                           _stream(self.device)), "mc_measure")

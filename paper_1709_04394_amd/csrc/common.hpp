@@ -1,0 +1,131 @@
+// common.hpp -- device helpers and internal launcher declarations of libmcspin.
+//
+// Everything device-side that more than one kernel file needs: the Philox4x32-10
+// block function, the random-stream counter layout, the byte-lazy 32-bit draw,
+// wave64 reductions, and the parameter structs the host side fills.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcs {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Sec. "Random number generation", counter-based generators):
+// ten rounds of  L' = mullo(R, M), R' = mulhi(R, M) ^ k ^ L  on the two word
+// pairs, with the 4x32 word permutation and a Weyl key schedule.  The key is
+// wave-uniform in every kernel here, so the key schedule runs on the scalar
+// unit and each round costs two 32x32->64 multiplies and two 3-input XORs.
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += kPhiloxW0;
+            k1 += kPhiloxW1;
+        }
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * c.x;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+                       (uint32_t)p0);
+    }
+    return c;
+}
+
+// Stream tags (counter word 3, bits 24..31).
+enum : uint32_t {
+    kTagInit = 1, kTagSweep = 2, kTagCoupling = 3, kTagResample = 4,
+    kTagMuca = 5, kTagMlpInit = 6, kTagSweepLo = 7, kTagMucaLo = 8
+};
+
+// Counter word 3: tag << 24 | phase << 23 | (sweep >> 32) & 0x7FFFFF.
+__host__ __device__ __forceinline__ uint32_t ctr_w3(uint32_t tag, uint32_t phase, uint64_t sweep)
+{
+    return (tag << 24) | ((phase & 1u) << 23) | ((uint32_t)(sweep >> 32) & 0x7FFFFFu);
+}
+
+__device__ __forceinline__ uint32_t byte_of(const uint4 &b, uint32_t k)
+{
+    const uint32_t w = (k & 8u) ? ((k & 4u) ? b.w : b.z) : ((k & 4u) ? b.y : b.x);
+    return (w >> ((k & 3u) * 8u)) & 0xFFu;
+}
+
+// A threshold T in [0, 2^32] split for the byte-lazy test r32 < T with
+// r32 = byte << 24 | low24:  byte < top  => accept;  byte > top  => reject;
+// byte == top => accept iff low24 < low.  T = 2^32 has top = 256.
+struct Thr {
+    uint32_t top;  // T >> 24, 0..256
+    uint32_t low;  // T & 0xFFFFFF
+};
+
+__host__ __device__ __forceinline__ Thr split_thr(uint64_t T)
+{
+    Thr t;
+    t.top = (uint32_t)(T >> 24);
+    t.low = (uint32_t)(T & 0xFFFFFFu);
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// wave64 reductions
+__device__ __forceinline__ long long wave_sum(long long v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Parameter blocks filled on the host.
+struct Geom {
+    int dims, Lx, Ly, Lz;
+    int64_t N;      // sites per lattice
+    int count;      // lattices (int8) or word lattices (msc64)
+};
+
+struct SweepTables {
+    // Metropolis: index k = dE / 4 (k = 1..3); heat-bath: index h + z (0..12)
+    Thr met[4];
+    Thr hb[13];     // heat-bath, index h + 6 for every dimension
+};
+
+struct SweepCall {
+    Geom g;
+    const int8_t *J;    // [dims][N] or nullptr
+    int rule;           // 0 Metropolis, 1 heat-bath
+    uint32_t seed_lo, seed_hi;
+    uint32_t replica0;
+    SweepTables tab;
+};
+
+// Launchers (defined in the kernel files).  They only enqueue work.
+hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t value, hipStream_t s);
+hipError_t launch_init_int8(const Geom &g, int8_t *spins, int start, uint64_t seed, uint32_t replica0,
+                            hipStream_t s);
+hipError_t launch_init_msc64(const Geom &g, uint64_t *words, int start, uint64_t seed, uint32_t replica0,
+                             hipStream_t s);
+hipError_t launch_couplings(const Geom &g, int8_t *J, uint64_t seed, hipStream_t s);
+
+hipError_t launch_measure_int8(const Geom &g, const int8_t *spins, const int8_t *J, int64_t *EM,
+                               hipStream_t s);
+hipError_t launch_measure_msc64(const Geom &g, const uint64_t *words, const int8_t *J, int64_t *EM,
+                                hipStream_t s);
+
+// generic in-place half-sweep, any even geometry, int8
+hipError_t launch_phase_int8(const SweepCall &c, int8_t *spins, uint64_t sweep, int phase, hipStream_t s);
+// generic in-place half-sweep, msc64
+hipError_t launch_phase_msc64(const SweepCall &c, uint64_t *words, uint64_t sweep, int phase, hipStream_t s);
+
+}  // namespace mcs

@@ -1,0 +1,98 @@
+"""Host-side checks of the C ABI (no GPU needed, no compute call made).
+
+* libmcspin.so loads and exports every function declared in include/*.h;
+* argument validation returns the documented codes before any device work
+  (only invalid calls are made here, so no pointer is ever dereferenced).
+"""
+import ctypes
+import glob
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+mcs = pytest.importorskip("paper_1709_04394_amd")
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b(mc_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_all_declared_symbols_exported():
+    lib = ctypes.CDLL(mcs.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(mcs.exported_symbols()) <= names
+
+
+def test_abi_version_and_strerror():
+    assert mcs.abi_version() == 1
+    for code in range(0, -8, -1):
+        assert mcs.strerror(code)
+    assert "unknown" in mcs.strerror(-99)
+
+
+@pytest.fixture
+def ctx():
+    h = ctypes.c_void_p()
+    assert mcs._lib.mc_ctx_create(ctypes.byref(h), 0) == 0
+    yield h
+    mcs._lib.mc_ctx_destroy(h)
+
+
+def _sweep(ctx, geom, args, spins=FAKE):
+    return mcs._lib.mc_sweep(ctx, ctypes.byref(geom), spins, None, ctypes.byref(args), None, None, 0, None)
+
+
+def test_ctx_create_rejects_bad_arguments():
+    assert mcs._lib.mc_ctx_create(None, 0) == mcs.MC_E_INVAL
+    h = ctypes.c_void_p()
+    assert mcs._lib.mc_ctx_create(ctypes.byref(h), -1) == mcs.MC_E_INVAL
+
+
+@pytest.mark.parametrize("shape,code", [((2, 5, 8, 1), mcs.MC_E_SHAPE), ((2, 2, 8, 1), mcs.MC_E_SHAPE),
+                                        ((2, 8, 8, 3), mcs.MC_E_SHAPE), ((3, 8, 8, 7), mcs.MC_E_SHAPE),
+                                        ((4, 8, 8, 8), mcs.MC_E_SHAPE)])
+def test_shape_errors(ctx, shape, code):
+    g = mcs.Geom(shape[0], shape[1], shape[2], shape[3], mcs.INT8, 1)
+    a = mcs.SweepArgs(0, 0.4, 1, 0, 0, 1)
+    assert _sweep(ctx, g, a) == code
+    assert b"extent" in mcs._lib.mc_ctx_last_error(ctx) or b"dims" in mcs._lib.mc_ctx_last_error(ctx) \
+        or b"Lz" in mcs._lib.mc_ctx_last_error(ctx)
+
+
+@pytest.mark.parametrize("beta", [-0.1, math.nan, math.inf])
+def test_beta_range(ctx, beta):
+    g = mcs.make_geom(2, 8)
+    assert _sweep(ctx, g, mcs.SweepArgs(0, beta, 1, 0, 0, 1)) == mcs.MC_E_RANGE
+
+
+def test_other_argument_errors(ctx):
+    g = mcs.make_geom(2, 8)
+    assert _sweep(ctx, g, mcs.SweepArgs(0, 0.4, 1, 0, 0, -1)) == mcs.MC_E_RANGE
+    assert _sweep(ctx, g, mcs.SweepArgs(7, 0.4, 1, 0, 0, 1)) == mcs.MC_E_INVAL
+    assert _sweep(ctx, g, mcs.SweepArgs(0, 0.4, 1, 0, 0, 1), spins=None) == mcs.MC_E_INVAL
+    assert _sweep(ctx, g, mcs.SweepArgs(0, 0.4, 1, 0, 1 << 55, 1)) == mcs.MC_E_RANGE
+    gm = mcs.make_geom(2, 8, layout=mcs.MSC64, count=2)
+    assert _sweep(ctx, gm, mcs.SweepArgs(0, 0.4, 1, 2 ** 32 - 64, 0, 1)) == mcs.MC_E_RANGE
+    bad_layout = mcs.Geom(2, 8, 8, 1, 5, 1)
+    assert _sweep(ctx, bad_layout, mcs.SweepArgs(0, 0.4, 1, 0, 0, 1)) == mcs.MC_E_INVAL
+    zero = mcs.Geom(2, 8, 8, 1, mcs.INT8, 0)
+    assert _sweep(ctx, zero, mcs.SweepArgs(0, 0.4, 1, 0, 0, 1)) == mcs.MC_E_RANGE
+    assert mcs._lib.mc_init(ctx, ctypes.byref(g), FAKE, 2, 1, 0, None) == mcs.MC_E_INVAL
+    assert mcs._lib.mc_init(ctx, ctypes.byref(g), None, 1, 1, 0, None) == mcs.MC_E_INVAL
+    assert mcs._lib.mc_measure(ctx, ctypes.byref(g), FAKE, None, None, None) == mcs.MC_E_INVAL
+    assert mcs._lib.mc_couplings(ctx, ctypes.byref(g), None, 1, None) == mcs.MC_E_INVAL
+    assert mcs._lib.mc_sweep(None, ctypes.byref(g), FAKE, None, None, None, None, 0, None) == mcs.MC_E_INVAL
