@@ -74,10 +74,13 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
  * over threads:
  *   ctr = (a, replica, sweep mod 2^32, tag<<24 | phase<<23 | (sweep>>32 & 0x7FFFFF))
  * A 32-bit uniform for item j is assembled from two Philox blocks:
- *   top byte  = byte (j mod 16) of Philox(tag,    a = j div 16)
- *   low 24 b  = word 0 of        Philox(tag_lo, a = j), masked to 24 bits
- * which is an exactly uniform 32-bit integer r; the uniform variate of the
- * paper is r / 2^32 in [0,1).                                                 */
+ *   top byte  = bit k (k = 0..7) is bit (j mod 16) of 16-bit half-word k of
+ *               Philox(tag, a = j div 16) (half-word k = bits 16(k mod 2) ..
+ *               16(k mod 2)+15 of output word k div 2), so one block holds
+ *               the top bytes of 16 consecutive items as 8 bit-planes;
+ *   low 24 b  = word 0 of Philox(tag_lo, a = j), masked to 24 bits;
+ * r = top << 24 | low is an exactly uniform 32-bit integer, and the uniform
+ * variate of the paper is r / 2^32 in [0,1).                                  */
 enum {
     ORC_TAG_INIT = 1, ORC_TAG_SWEEP = 2, ORC_TAG_COUPLING = 3, ORC_TAG_RESAMPLE = 4,
     ORC_TAG_MUCA = 5, ORC_TAG_MLP_INIT = 6, ORC_TAG_SWEEP_LO = 7, ORC_TAG_MUCA_LO = 8
@@ -100,8 +103,12 @@ uint32_t orc_draw_byte(uint64_t seed, uint32_t tag, uint32_t j, uint32_t replica
 {
     uint32_t out[4];
     orc_block(seed, tag, j >> 4, replica, sweep, phase, out);
-    uint32_t byte_index = j & 15u;
-    return (out[byte_index >> 2] >> (8u * (byte_index & 3u))) & 0xFFu;
+    uint32_t pos = j & 15u, byte = 0;
+    for (uint32_t k = 0; k < 8; ++k) {
+        uint32_t halfword = (out[k >> 1] >> (16u * (k & 1u))) & 0xFFFFu;
+        byte |= ((halfword >> pos) & 1u) << k;
+    }
+    return byte;
 }
 
 uint32_t orc_draw32(uint64_t seed, uint32_t tag, uint32_t tag_lo, uint32_t j,

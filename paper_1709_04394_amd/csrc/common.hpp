@@ -49,10 +49,35 @@ __host__ __device__ __forceinline__ uint32_t ctr_w3(uint32_t tag, uint32_t phase
     return (tag << 24) | ((phase & 1u) << 23) | ((uint32_t)(sweep >> 32) & 0x7FFFFFu);
 }
 
-__device__ __forceinline__ uint32_t byte_of(const uint4 &b, uint32_t k)
+// The top byte of the 32-bit draw of item j lives in the Philox block of
+// a = j / 16 as eight bit-planes: bit k of the byte is bit (j mod 16) of
+// 16-bit half-word k of the block (half-word k = bits 16 (k mod 2) .. +15 of
+// word k / 2).  One block thus serves 16 consecutive items, and a pair of
+// blocks gives 32 items' planes as eight 32-bit words (plane_pair below),
+// which is the form the bit-sliced sweep kernels consume.
+__device__ __forceinline__ uint32_t byte_of(const uint4 &b, uint32_t pos)
 {
-    const uint32_t w = (k & 8u) ? ((k & 4u) ? b.w : b.z) : ((k & 4u) ? b.y : b.x);
-    return (w >> ((k & 3u) * 8u)) & 0xFFu;
+    const uint32_t w[4] = {b.x, b.y, b.z, b.w};
+    uint32_t byte = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) byte |= ((w[k >> 1] >> (16u * (k & 1u) + pos)) & 1u) << k;
+    return byte;
+}
+
+// Bit 7 of byte_of(b, pos): the byte is < 128 iff this is 0.
+__device__ __forceinline__ uint32_t top_bit_of(const uint4 &b, uint32_t pos)
+{
+    return (b.w >> (16u + pos)) & 1u;
+}
+
+// Plane k (k = 0..7) of the 32 items 32q .. 32q+31 from blocks A = block(2q)
+// and B = block(2q+1): low half-word from A, high half-word from B.
+__device__ __forceinline__ uint32_t plane_pair(const uint4 &A, const uint4 &B, int k)
+{
+    const uint32_t a = (k >> 1) == 0 ? A.x : (k >> 1) == 1 ? A.y : (k >> 1) == 2 ? A.z : A.w;
+    const uint32_t b = (k >> 1) == 0 ? B.x : (k >> 1) == 1 ? B.y : (k >> 1) == 2 ? B.z : B.w;
+    // bytes (little-endian) of the result: a.lo16 | b.lo16 << 16, or the hi16s
+    return (k & 1) ? __builtin_amdgcn_perm(b, a, 0x07060302u) : __builtin_amdgcn_perm(b, a, 0x05040100u);
 }
 
 // A threshold T in [0, 2^32] split for the byte-lazy test r32 < T with

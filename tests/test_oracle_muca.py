@@ -69,20 +69,25 @@ def test_exact_weights_give_flat_histogram():
 
 
 def test_canonical_weights_reproduce_boltzmann():
-    L, W, beta = 8, 256, 0.3
+    L, W, beta = 8, 64, 0.3
     N = L * L
     K = oracle.muca_levels(L)
     lnW = np.array([-beta * (4 * k - 2 * N) for k in range(K)])
-    spins, E = oracle.muca_start(L, W, 12)
-    oracle.muca_sweeps(L, spins, E, lnW, 12, 0, 50, False)
-    H = oracle.muca_sweeps(L, spins, E, lnW, 12, 50, 200, True)
     lng = _exact_window_lng(L)
     logp = np.where(np.isfinite(lng), lng + lnW, -np.inf)
     p = np.exp(logp - logp.max())
     p /= p.sum()
-    ph = H / H.sum()
-    big = p > 0.01
-    assert np.max(np.abs(ph[big] - p[big]) / p[big]) < 0.05
+    # 8 independent groups of walkers (own seeds) give the spread of the estimate
+    est = []
+    for grp in range(8):
+        spins, E = oracle.muca_start(L, W, 100 + grp)
+        oracle.muca_sweeps(L, spins, E, lnW, 100 + grp, 0, 50, False)
+        H = oracle.muca_sweeps(L, spins, E, lnW, 100 + grp, 50, 200, True)
+        est.append(H / H.sum())
+    est = np.array(est)
+    mean, sig = est.mean(axis=0), est.std(axis=0, ddof=1) / np.sqrt(len(est))
+    big = p > 0.005
+    assert np.all(np.abs(mean[big] - p[big]) < 5 * sig[big] + 1e-3), np.max(np.abs(mean[big] - p[big]) / sig[big])
 
 
 def test_plain_recursion_converges_to_exact_lng():
