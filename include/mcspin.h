@@ -127,10 +127,34 @@ size_t mc_sweep_workspace_bytes(const mc_geom *geom);
 int mc_sweep(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *J, const mc_sweep_args *args,
              int64_t *EM, void *ws, size_t ws_bytes, void *stream);
 
+/* As mc_sweep for MC_INT8 lattices, but lattice l runs at inverse temperature
+ * betas[l] (host array of geom->count entries; args->beta is ignored).  The
+ * results of lattice l are exactly those of mc_sweep on that lattice alone
+ * with replica0 + l at betas[l]; batching only lets one launch carry all of
+ * them (taller bands, less redone halo).                                   */
+int mc_sweep_betas(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *J, const mc_sweep_args *args,
+                   const double *betas, int64_t *EM, void *ws, size_t ws_bytes, void *stream);
+
 /* E and M of every lattice (lane) as in mc_sweep; EM: device int64
  * [count * lanes][2].  Stream-ordered.                                      */
 int mc_measure(mc_ctx *ctx, const mc_geom *geom, const void *spins, const int8_t *J, int64_t *EM,
                void *stream);
+
+/* Launch shape of the fused 2D sweep (int8, J = 1, Metropolis, Lx a multiple
+ * of 64): band height H (rows per workgroup), K sweeps per launch and threads
+ * per workgroup.  The shape changes speed only, never results (the
+ * determinism contract above).  mc_set_tile_plan fixes it for the geometry's
+ * (Lx, Ly, count) on this context; mc_get_tile_plan reports the shape in use
+ * (the tuned or set one, else a default).  Host-only calls.                 */
+int mc_set_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t H, int32_t K, int32_t threads);
+int mc_get_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t *H, int32_t *K, int32_t *threads);
+
+/* Autotuner: times every admissible (H, K, threads) for this geometry with
+ * `sweeps` sweeps at inverse temperature beta on two caller-provided scratch
+ * lattices (device, count * N bytes each; overwritten) and keeps the fastest
+ * shape on the context.  Synchronises the stream.                          */
+int mc_tune_sweep(mc_ctx *ctx, const mc_geom *geom, void *scratch_a, void *scratch_b, double beta,
+                  int32_t sweeps, void *stream);
 
 #ifdef __cplusplus
 }

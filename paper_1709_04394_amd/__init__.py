@@ -76,6 +76,14 @@ _lib_fns = dict(
     mc_sweep=_sig("mc_sweep", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _c.POINTER(SweepArgs), _vp, _vp,
                                          _c.c_size_t, _vp]),
     mc_measure=_sig("mc_measure", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _vp, _vp]),
+    mc_sweep_betas=_sig("mc_sweep_betas", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _c.POINTER(SweepArgs),
+                                                     _c.POINTER(_c.c_double), _vp, _vp, _c.c_size_t, _vp]),
+    mc_set_tile_plan=_sig("mc_set_tile_plan", _c.c_int, [_vp, _c.POINTER(Geom), _c.c_int32, _c.c_int32,
+                                                         _c.c_int32]),
+    mc_get_tile_plan=_sig("mc_get_tile_plan", _c.c_int, [_vp, _c.POINTER(Geom), _c.POINTER(_c.c_int32),
+                                                         _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
+    mc_tune_sweep=_sig("mc_tune_sweep", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _c.c_double, _c.c_int32,
+                                                   _vp]),
 )
 
 
@@ -166,6 +174,30 @@ class Context:
         return self._check(_lib.mc_sweep(self._h, ctypes.byref(geom), _ptr(spins), _ptr(J), ctypes.byref(a),
                                          _ptr(EM), _ptr(ws), wsb, _stream(self.device)), "mc_sweep")
 
+    def sweep_betas(self, geom, spins, betas, seed, nsweeps, sweep0=0, replica0=0, rule=METROPOLIS, J=None,
+                    EM=None, ws=None):
+        if len(betas) != geom.count:
+            raise ValueError("need one beta per lattice")
+        b = (ctypes.c_double * geom.count)(*[float(x) for x in betas])
+        a = SweepArgs(rule, float(betas[0]), seed, replica0, sweep0, nsweeps)
+        wsb = 0 if ws is None else ws.numel() * ws.element_size()
+        return self._check(_lib.mc_sweep_betas(self._h, ctypes.byref(geom), _ptr(spins), _ptr(J), ctypes.byref(a), b,
+                                               _ptr(EM), _ptr(ws), wsb, _stream(self.device)), "mc_sweep_betas")
+
     def measure(self, geom, spins, EM, J=None):
         return self._check(_lib.mc_measure(self._h, ctypes.byref(geom), _ptr(spins), _ptr(J), _ptr(EM),
                                            _stream(self.device)), "mc_measure")
+
+    def set_tile_plan(self, geom, H, K, threads):
+        return self._check(_lib.mc_set_tile_plan(self._h, ctypes.byref(geom), H, K, threads), "mc_set_tile_plan")
+
+    def get_tile_plan(self, geom):
+        H, K, T = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(_lib.mc_get_tile_plan(self._h, ctypes.byref(geom), ctypes.byref(H), ctypes.byref(K),
+                                          ctypes.byref(T)), "mc_get_tile_plan")
+        return H.value, K.value, T.value
+
+    def tune_sweep(self, geom, scratch_a, scratch_b, beta, sweeps=20):
+        self._check(_lib.mc_tune_sweep(self._h, ctypes.byref(geom), _ptr(scratch_a), _ptr(scratch_b), float(beta),
+                                       sweeps, _stream(self.device)), "mc_tune_sweep")
+        return self.get_tile_plan(geom)

@@ -5,17 +5,13 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/mcspin.h"
 #include "common.hpp"
 #include "internal.hpp"
 
 using namespace mcs;
-
-struct mc_ctx {
-    int device = 0;
-    std::string last_error;
-};
 
 namespace mcs {
 
@@ -205,9 +201,64 @@ int mc_sweep(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *J, con
     c.seed_hi = (uint32_t)(args->seed >> 32);
     c.replica0 = args->replica0;
     c.tab = build_tables(args->beta);
+    c.per_lattice = 0;
+    c.tabs = nullptr;
     hipStream_t s = (hipStream_t)stream;
     const int64_t em_stride = 2 * (int64_t)geom->count * (int64_t)lanes;
     return run_sweeps(ctx, c, geom->layout, spins, args->sweep0, args->nsweeps, EM, em_stride, ws, ws_bytes, s);
+}
+
+int mc_sweep_betas(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *J, const mc_sweep_args *args,
+                   const double *betas, int64_t *EM, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx) return MC_E_INVAL;
+    int rc = check_geom(ctx, geom, true);
+    if (rc) return rc;
+    if (!betas) return fail(ctx, MC_E_INVAL, "betas is NULL");
+    if (geom->layout != MC_INT8) return fail(ctx, MC_E_LAYOUT, "per-lattice temperatures need MC_INT8");
+    for (int l = 0; l < geom->count; ++l)
+        if (!(betas[l] >= 0.0) || std::isinf(betas[l])) return fail(ctx, MC_E_RANGE, "betas[%d] out of range", l);
+    mc_sweep_args a1 = args ? *args : mc_sweep_args{};
+    if (!args) return fail(ctx, MC_E_INVAL, "args is NULL");
+    a1.beta = betas[0];
+    // common argument checks (spins, rule, counts) through the single-beta path's rules
+    if (!spins) return fail(ctx, MC_E_INVAL, "spins is NULL");
+    if (a1.rule != MC_METROPOLIS && a1.rule != MC_HEATBATH) return fail(ctx, MC_E_INVAL, "unknown rule %d", a1.rule);
+    if (a1.nsweeps < 0) return fail(ctx, MC_E_RANGE, "nsweeps must be >= 0");
+    if (a1.sweep0 + (uint64_t)a1.nsweeps >= (1ull << 55)) return fail(ctx, MC_E_RANGE, "sweep numbers must stay below 2^55");
+    if ((uint64_t)a1.replica0 + (uint64_t)geom->count > 4294967296ull)
+        return fail(ctx, MC_E_RANGE, "replica ids exceed 32 bits");
+    if (a1.nsweeps == 0) return MC_OK;
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t em_stride = 2 * (int64_t)geom->count;
+    std::vector<SweepTables> tabs((size_t)geom->count);
+    for (int l = 0; l < geom->count; ++l) tabs[(size_t)l] = build_tables(betas[l]);
+    SweepCall c;
+    c.g = to_geom(geom);
+    c.J = J;
+    c.rule = a1.rule;
+    c.seed_lo = (uint32_t)a1.seed;
+    c.seed_hi = (uint32_t)(a1.seed >> 32);
+    c.replica0 = a1.replica0;
+    c.tab = tabs[0];
+    c.per_lattice = 1;
+    c.tabs = tabs.data();
+    if (tile2d_supported(c, MC_INT8) && ws && ws_bytes >= fused_workspace_bytes(c.g, MC_INT8))
+        return run_sweeps(ctx, c, MC_INT8, spins, a1.sweep0, a1.nsweeps, EM, em_stride, ws, ws_bytes, s);
+    // otherwise one lattice at a time
+    for (int l = 0; l < geom->count; ++l) {
+        SweepCall c1 = c;
+        c1.g.count = 1;
+        c1.replica0 = a1.replica0 + (uint32_t)l;
+        c1.tab = tabs[(size_t)l];
+        c1.per_lattice = 0;
+        c1.tabs = nullptr;
+        rc = run_sweeps(ctx, c1, MC_INT8, (int8_t *)spins + (int64_t)l * c.g.N, a1.sweep0, a1.nsweeps,
+                        EM ? EM + 2 * l : nullptr, em_stride, nullptr, 0, s);
+        if (rc) return rc;
+    }
+    return MC_OK;
 }
 
 int mc_measure(mc_ctx *ctx, const mc_geom *geom, const void *spins, const int8_t *J, int64_t *EM, void *stream)

@@ -21,6 +21,21 @@ constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
 constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 
+// gfx950's v_bitop3_b32 evaluates any 3-input boolean function in one
+// instruction; the immediate is the truth table f(0xF0, 0xCC, 0xAA) of the
+// operands (a, b, c).  BOP3(a, b, c, expr) spells the function with A, B, C.
+template <unsigned IMM>
+__device__ __forceinline__ uint32_t bop3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, (unsigned char)IMM);
+}
+#define MCS_A 0xF0u
+#define MCS_B 0xCCu
+#define MCS_C 0xAAu
+#define MCS_BOP3(a, b, c, expr) ::mcs::bop3<((expr)&0xFFu)>((a), (b), (c))
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) { return bop3<0x96u>(a, b, c); }
+
 __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
@@ -31,7 +46,7 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
         }
         const uint64_t p0 = (uint64_t)kPhiloxM0 * c.x;
         const uint64_t p1 = (uint64_t)kPhiloxM1 * c.z;
-        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+        c = make_uint4(xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1, xor3((uint32_t)(p0 >> 32), c.w, k1),
                        (uint32_t)p0);
     }
     return c;
@@ -126,13 +141,18 @@ struct SweepTables {
     Thr hb[13];     // heat-bath, index h + 6 for every dimension
 };
 
+// most lattices one fused launch can carry with their own temperature
+constexpr int kMaxTableLattices = 16;
+
 struct SweepCall {
     Geom g;
     const int8_t *J;    // [dims][N] or nullptr
     int rule;           // 0 Metropolis, 1 heat-bath
     uint32_t seed_lo, seed_hi;
     uint32_t replica0;
-    SweepTables tab;
+    SweepTables tab;    // tables of the common temperature
+    int per_lattice;    // 1: lattice l uses tabs[l] (host array, host code only)
+    const SweepTables *tabs;
 };
 
 // Launchers (defined in the kernel files).  They only enqueue work.

@@ -3,9 +3,31 @@
 
 #include <cstdarg>
 #include <cstddef>
+#include <map>
+#include <string>
+#include <tuple>
 
 #include "../../include/mcspin.h"
 #include "common.hpp"
+
+namespace mcs {
+
+// Launch shape of the fused 2D sweep: band height, sweeps per launch and
+// threads per workgroup.  Any choice gives the same results.
+struct TilePlan {
+    int H = 16;
+    int K = 2;
+    int threads = 512;
+};
+
+}  // namespace mcs
+
+struct mc_ctx {
+    int device = 0;
+    std::string last_error;
+    // tuned launch shapes keyed by (Lx, Ly, count)
+    std::map<std::tuple<int, int, int>, mcs::TilePlan> tile_plans;
+};
 
 namespace mcs {
 
@@ -16,8 +38,15 @@ int check_geom(mc_ctx *ctx, const mc_geom *g, bool need_count);
 Geom to_geom(const mc_geom *g);
 SweepTables build_tables(double beta);
 
-// Sweep driver: chooses the fused single-pass kernel when the geometry and the
-// workspace allow it, the generic two-launch half-sweeps otherwise.
+// fused 2D kernel (k_tile2d.hip)
+bool tile2d_supported(const SweepCall &c, int layout);
+size_t tile2d_lds_bytes(int Lx, int H, int K);
+hipError_t launch_tile2d(const SweepCall &c, const int8_t *src, int8_t *dst, uint64_t sweep0, int k, int H,
+                         int threads, int64_t *EM, int64_t em_stride, int64_t em_sweep0, hipStream_t s);
+TilePlan default_tile_plan(const Geom &g);
+
+// Sweep driver: chooses the fused kernel when the geometry and the workspace
+// allow it, the generic two-launch half-sweeps otherwise.
 size_t fused_workspace_bytes(const Geom &g, int layout);
 int run_sweeps(mc_ctx *ctx, const SweepCall &c, int layout, void *spins, uint64_t sweep0, int nsweeps,
                int64_t *EM, int64_t em_stride, void *ws, size_t ws_bytes, hipStream_t s);

@@ -1,21 +1,89 @@
-// sweep_driver.hip -- sequencing of half-sweeps, fused sweeps and per-sweep
-// measurement for mc_sweep.
+// sweep_driver.hip -- sequencing of half-sweeps, fused multi-sweep launches
+// and per-sweep measurement for mc_sweep, and the launch-shape autotuner.
+#include <algorithm>
+#include <vector>
+
 #include "internal.hpp"
 
 namespace mcs {
 
 size_t fused_workspace_bytes(const Geom &g, int layout)
 {
-    (void)g;
-    (void)layout;
+    if (layout == MC_INT8 && g.dims == 2 && g.Lx % 64 == 0 && g.Lx <= 16384)
+        return (size_t)g.count * (size_t)g.N;
     return 0;
+}
+
+// Default launch shape: enough bands to give every CU work, sweeps per launch
+// limited so the redone halo stays small.
+TilePlan default_tile_plan(const Geom &g)
+{
+    TilePlan p;
+    const int want_tiles = 256;
+    const int64_t per = std::max<int64_t>(1, (int64_t)want_tiles / std::max(1, g.count));
+    int H = (int)std::max<int64_t>(4, g.Ly / per);
+    H = std::min(H, 64);
+    H = std::min(H, g.Ly);
+    p.H = H;
+    p.K = H >= 16 ? 2 : 1;
+    while (p.K > 1 && tile2d_lds_bytes(g.Lx, p.H, p.K) > 65536) --p.K;
+    while (p.H > 4 && tile2d_lds_bytes(g.Lx, p.H, p.K) > 65536) p.H /= 2;
+    const int tasks = (p.H + 2 * p.K) * (g.Lx / 64);
+    p.threads = std::min(1024, std::max(64, ((tasks + 63) / 64) * 64));
+    return p;
+}
+
+static bool plan_ok(const Geom &g, const TilePlan &p)
+{
+    return p.H >= 1 && p.K >= 1 && p.K <= 8 && p.threads >= 64 && p.threads <= 1024 && p.threads % 64 == 0 &&
+           tile2d_lds_bytes(g.Lx, std::min(p.H, g.Ly), p.K) <= 65536;
+}
+
+static TilePlan plan_for(mc_ctx *ctx, const Geom &g)
+{
+    auto it = ctx->tile_plans.find(std::make_tuple(g.Lx, g.Ly, g.count));
+    if (it != ctx->tile_plans.end()) return it->second;
+    return default_tile_plan(g);
+}
+
+// Split n sweeps into launches of at most K sweeps, preferring an even number
+// of launches so the result lands back in the caller's buffer.
+static std::vector<int> split_launches(int n, int K)
+{
+    int m = (n + K - 1) / K;
+    if ((m & 1) && m < n) ++m;
+    std::vector<int> sizes(m, n / m);
+    for (int i = 0; i < n % m; ++i) sizes[i] += 1;
+    return sizes;
+}
+
+static int run_fused(mc_ctx *ctx, const SweepCall &c, const TilePlan &p, int8_t *spins, int8_t *ws,
+                     uint64_t sweep0, int nsweeps, int64_t *EM, int64_t em_stride, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    if (EM) e = launch_fill_i64(EM, (int64_t)nsweeps * em_stride, 0, s);
+    const std::vector<int> sizes = split_launches(nsweeps, p.K);
+    int done = 0;
+    const int H = std::min(p.H, c.g.Ly);
+    for (size_t i = 0; i < sizes.size() && e == hipSuccess; ++i) {
+        const int8_t *src = (i & 1) ? ws : spins;
+        int8_t *dst = (i & 1) ? spins : ws;
+        e = launch_tile2d(c, src, dst, sweep0 + (uint64_t)done, sizes[i], H, p.threads, EM, em_stride, done, s);
+        done += sizes[i];
+    }
+    if (e == hipSuccess && (sizes.size() & 1))
+        e = hipMemcpyAsync(spins, ws, (size_t)c.g.count * (size_t)c.g.N, hipMemcpyDeviceToDevice, s);
+    return device_check(ctx, e, "mc_sweep fused launch");
 }
 
 int run_sweeps(mc_ctx *ctx, const SweepCall &c, int layout, void *spins, uint64_t sweep0, int nsweeps,
                int64_t *EM, int64_t em_stride, void *ws, size_t ws_bytes, hipStream_t s)
 {
-    (void)ws;
-    (void)ws_bytes;
+    if (tile2d_supported(c, layout) && ws && ws_bytes >= fused_workspace_bytes(c.g, layout)) {
+        const TilePlan p = plan_for(ctx, c.g);
+        if (plan_ok(c.g, p))
+            return run_fused(ctx, c, p, (int8_t *)spins, (int8_t *)ws, sweep0, nsweeps, EM, em_stride, s);
+    }
     for (int t = 0; t < nsweeps; ++t) {
         const uint64_t sweep = sweep0 + (uint64_t)t;
         hipError_t e = hipSuccess;
@@ -31,3 +99,105 @@ int run_sweeps(mc_ctx *ctx, const SweepCall &c, int layout, void *spins, uint64_
 }
 
 }  // namespace mcs
+
+using namespace mcs;
+
+extern "C" {
+
+int mc_set_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t H, int32_t K, int32_t threads)
+{
+    if (!ctx) return MC_E_INVAL;
+    int rc = check_geom(ctx, geom, true);
+    if (rc) return rc;
+    const Geom g = to_geom(geom);
+    TilePlan p;
+    p.H = H;
+    p.K = K;
+    p.threads = threads;
+    if (!plan_ok(g, p)) return fail(ctx, MC_E_RANGE, "tile plan H=%d K=%d threads=%d not usable", H, K, threads);
+    ctx->tile_plans[std::make_tuple(g.Lx, g.Ly, g.count)] = p;
+    return MC_OK;
+}
+
+int mc_get_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t *H, int32_t *K, int32_t *threads)
+{
+    if (!ctx || !H || !K || !threads) return MC_E_INVAL;
+    int rc = check_geom(ctx, geom, true);
+    if (rc) return rc;
+    const TilePlan p = plan_for(ctx, to_geom(geom));
+    *H = p.H;
+    *K = p.K;
+    *threads = p.threads;
+    return MC_OK;
+}
+
+int mc_tune_sweep(mc_ctx *ctx, const mc_geom *geom, void *scratch_a, void *scratch_b, double beta, int32_t sweeps,
+                  void *stream)
+{
+    if (!ctx) return MC_E_INVAL;
+    int rc = check_geom(ctx, geom, true);
+    if (rc) return rc;
+    if (!scratch_a || !scratch_b) return fail(ctx, MC_E_INVAL, "scratch buffers are NULL");
+    if (!(beta >= 0.0) || sweeps < 1 || sweeps > 1000) return fail(ctx, MC_E_RANGE, "beta or sweeps out of range");
+    const Geom g = to_geom(geom);
+    SweepCall c;
+    c.g = g;
+    c.J = nullptr;
+    c.rule = MC_METROPOLIS;
+    c.seed_lo = 1;
+    c.seed_hi = 0;
+    c.replica0 = 0;
+    c.tab = build_tables(beta);
+    c.per_lattice = 0;
+    c.tabs = nullptr;
+    if (!tile2d_supported(c, geom->layout)) return fail(ctx, MC_E_LAYOUT, "no tunable kernel for this geometry");
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(ctx, MC_E_DEVICE, "hipEventCreate failed");
+    hipError_t e = launch_init_int8(g, (int8_t *)scratch_a, 1, 1, 0, s);
+    TilePlan best = default_tile_plan(g);
+    float best_ms = 1e30f;
+    const int Hs[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128};
+    const int Ks[] = {1, 2, 3, 4, 6, 8};
+    const int Ts[] = {256, 512, 1024};
+    for (int H : Hs) {
+        if (H > g.Ly) continue;
+        for (int K : Ks)
+            for (int T : Ts) {
+                TilePlan p;
+                p.H = H;
+                p.K = K;
+                p.threads = T;
+                if (!plan_ok(g, p) || e != hipSuccess) continue;
+                int n = std::max(sweeps, 2 * K);
+                n -= n % (2 * K);
+                // warm-up launch, then timed launches
+                e = launch_tile2d(c, (int8_t *)scratch_a, (int8_t *)scratch_b, 0, K, H, T, nullptr, 0, 0, s);
+                if (e != hipSuccess) break;
+                hipEventRecord(e0, s);
+                for (int i = 0; i < n / K && e == hipSuccess; ++i)
+                    e = launch_tile2d(c, (i & 1) ? (int8_t *)scratch_b : (int8_t *)scratch_a,
+                                      (i & 1) ? (int8_t *)scratch_a : (int8_t *)scratch_b, (uint64_t)i * K, K, H, T,
+                                      nullptr, 0, 0, s);
+                hipEventRecord(e1, s);
+                if (e != hipSuccess) break;
+                if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+                float ms = 0;
+                hipEventElapsedTime(&ms, e0, e1);
+                ms /= (float)n;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = p;
+                }
+            }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) return device_check(ctx, e, "mc_tune_sweep");
+    ctx->tile_plans[std::make_tuple(g.Lx, g.Ly, g.count)] = best;
+    return MC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+"""GPU parity of the fused multi-sweep 2D kernel (band tiles in LDS, K sweeps
+per launch with a redone halo) against the CPU oracle, and launch-shape
+invariance: every admissible (band height, sweeps per launch, threads) gives
+the same bits, including ragged last bands, bands taller than the lattice,
+an odd number of launches (result copied back), several lattices per launch
+and sweep numbers above 2^32.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+mcs = pytest.importorskip("paper_1709_04394_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return mcs.Context(0)
+
+
+def _gpu_run(ctx, shape, beta, seed, nsweeps, sweep0, count, replica0, plan):
+    g = mcs.make_geom(2, shape, count=count)
+    spins = mcs.lattice_tensor(g)
+    ctx.init(g, spins, mcs.HOT, seed, replica0)
+    ws = torch.empty(ctx.sweep_workspace_bytes(g), dtype=torch.uint8, device="cuda")
+    assert ws.numel() == count * g.N
+    if plan is not None:
+        ctx.set_tile_plan(g, *plan)
+    EM = torch.empty((nsweeps, count, 2), dtype=torch.int64, device="cuda")
+    ctx.sweep(g, spins, beta, seed, nsweeps, sweep0=sweep0, replica0=replica0, EM=EM, ws=ws)
+    torch.cuda.synchronize()
+    return spins.cpu().numpy(), EM.cpu().numpy()
+
+
+def _oracle_run(shape, beta, seed, nsweeps, sweep0, count, replica0):
+    out_s, out_em = [], []
+    for l in range(count):
+        s = oracle.init(2, shape, oracle.HOT, seed, replica0 + l)
+        em = oracle.sweep(2, shape, s, beta, seed, replica0 + l, sweep0, nsweeps)
+        out_s.append(s)
+        out_em.append(em)
+    return np.stack(out_s), np.stack(out_em, axis=1)
+
+
+@pytest.mark.parametrize("shape,plan", [((64, 64), (4, 1, 64)), ((64, 64), (8, 2, 128)), ((64, 64), (16, 3, 256)),
+                                        ((64, 64), (5, 4, 512)), ((64, 64), (64, 8, 1024)),
+                                        ((128, 36), (7, 2, 192)), ((192, 20), (64, 3, 256)),
+                                        ((64, 4), (2, 1, 64)), ((64, 6), (4, 4, 128)), ((256, 132), None)])
+@pytest.mark.parametrize("nsweeps", [1, 3, 8])
+def test_fused_matches_oracle(ctx, shape, plan, nsweeps):
+    beta, seed, sweep0, count, rep0 = 0.4406868, 29, (1 << 32) - 2, 2, 3
+    gs, gem = _gpu_run(ctx, shape, beta, seed, nsweeps, sweep0, count, rep0, plan)
+    os_, oem = _oracle_run(shape, beta, seed, nsweeps, sweep0, count, rep0)
+    assert np.array_equal(gs, os_)
+    assert np.array_equal(gem, oem)
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.2, 0.5, 3.0])
+def test_fused_betas(ctx, beta):
+    gs, gem = _gpu_run(ctx, (128, 64), beta, 4, 6, 0, 1, 0, (8, 2, 256))
+    os_, oem = _oracle_run((128, 64), beta, 4, 6, 0, 1, 0)
+    assert np.array_equal(gs, os_) and np.array_equal(gem, oem)
+
+
+def test_fused_large_lattice_prefix(ctx):
+    # 4096^2 at beta_c: the bench's lattice, first sweeps compared in full
+    shape = (4096, 4096)
+    gs, gem = _gpu_run(ctx, shape, 0.44068679350977147, 7, 4, 0, 1, 1, None)
+    os_, oem = _oracle_run(shape, 0.44068679350977147, 7, 4, 0, 1, 1)
+    assert np.array_equal(gem, oem)
+    assert np.array_equal(gs, os_)
+
+
+@pytest.mark.parametrize("shape,use_ws", [((256, 64), True), ((64, 100), True), ((36, 20), False), ((64, 8), False)])
+def test_sweep_betas_per_lattice(ctx, shape, use_ws):
+    # one call, lattice l at betas[l]: equals the oracle run of each lattice alone
+    betas = [0.40, 0.44068679350977147, 0.50]
+    seed, nsw, rep0 = 7, 5, 10
+    g = mcs.make_geom(2, shape, count=3)
+    spins = mcs.lattice_tensor(g)
+    ctx.init(g, spins, mcs.HOT, seed, rep0)
+    ws = torch.empty(max(1, ctx.sweep_workspace_bytes(g)), dtype=torch.uint8, device="cuda") if use_ws else None
+    EM = torch.empty((nsw, 3, 2), dtype=torch.int64, device="cuda")
+    ctx.sweep_betas(g, spins, betas, seed, nsw, sweep0=11, replica0=rep0, EM=EM, ws=ws)
+    torch.cuda.synchronize()
+    gs, gem = spins.cpu().numpy(), EM.cpu().numpy()
+    for l, b in enumerate(betas):
+        s = oracle.init(2, shape, oracle.HOT, seed, rep0 + l)
+        em = oracle.sweep(2, shape, s, b, seed, rep0 + l, 11, nsw)
+        assert np.array_equal(gs[l], s), l
+        assert np.array_equal(gem[:, l, :], em), l
+
+
+def test_tuner_picks_equivalent_plan(ctx):
+    g = mcs.make_geom(2, (256, 128))
+    a = mcs.lattice_tensor(g)
+    b = mcs.lattice_tensor(g)
+    plan = ctx.tune_sweep(g, a, b, 0.44, sweeps=4)
+    assert plan[0] >= 1 and plan[1] >= 1
+    gs, gem = _gpu_run(ctx, (256, 128), 0.44, 3, 5, 0, 1, 0, plan)
+    os_, oem = _oracle_run((256, 128), 0.44, 3, 5, 0, 1, 0)
+    assert np.array_equal(gs, os_) and np.array_equal(gem, oem)
