@@ -4,9 +4,9 @@
 Workload (the paper's benchmark size, Sec. "Checkerboard scheme": L = 4096):
 three 4096 x 4096 periodic 2D Ising lattices, int8 spins, hot start from seed
 7, checkerboard Metropolis at beta in {0.40, beta_c, 0.50}, Philox4x32-10
-randomness, (E, M) recorded after every sweep.  One step = ten full sweeps of
+randomness, (E, M) recorded after every sweep.  One step = sixteen full sweeps of
 each of the three lattices, including the per-sweep measurement; the default
-1000 steps are the 10^4 sweeps per temperature of that workload.
+625 steps are the 10^4 sweeps per temperature of that workload.
 
 Prints one JSON line: spin flips per ns (attempted single-site updates per ns,
 the inverse of the paper's t_flip), the roofline fraction of the dominant
@@ -29,13 +29,13 @@ L = 4096
 SEED = 7
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_FLIP = 2.0
-SWEEPS_PER_STEP = 10
+SWEEPS_PER_STEP = 16
 
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=1000)
+    p.add_argument("--steps", type=int, default=625)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)

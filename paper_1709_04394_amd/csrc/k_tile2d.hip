@@ -30,7 +30,10 @@
 
 namespace mcs {
 
-constexpr int kTieQueue = 1024;
+// Tie-queue items per workgroup (split evenly over its waves).  A wave expects
+// about 0.6 * 32 / 256 ~ 0.075 ties per 32-site task; a full segment falls
+// back to drawing the tie in place.
+constexpr int kTieQueue = 512;
 
 struct Tile2DArgs {
     const int8_t *src;
@@ -47,25 +50,37 @@ struct Tile2DArgs {
     int64_t em_sweep0;              // index of this launch's first sweep within EM
 };
 
-// lt = (X < top), eq = (X == top) per bit, X given as planes X[7] (MSB) .. X[0].
-__device__ __forceinline__ void compare_planes(const uint32_t (&X)[8], uint32_t top, uint32_t &lt, uint32_t &eq)
+// Bit masks of a threshold's top byte: tk[k] = all ones iff bit k of top is
+// set (wave-uniform, lives in scalar registers); top = 256 (T = 2^32) is the
+// "always" case.
+struct TopMask {
+    uint32_t tk[8];
+    bool always;
+};
+
+__device__ __forceinline__ TopMask top_mask(uint32_t top)
 {
-    if (top >= 256u) {
-        lt = ~0u;
-        eq = 0u;
-        return;
-    }
-    lt = 0u;
-    eq = ~0u;
+    TopMask m;
 #pragma unroll
-    for (int k = 7; k >= 0; --k) {
-        if ((top >> k) & 1u) {
-            lt = MCS_BOP3(lt, eq, X[k], MCS_A | (MCS_B & ~MCS_C));  // lt | (eq & ~X)
-            eq &= X[k];
-        } else {
-            eq = MCS_BOP3(eq, X[k], 0u, MCS_A & ~MCS_B);  // eq & ~X
-        }
+    for (int k = 0; k < 8; ++k) m.tk[k] = ((top >> k) & 1u) ? ~0u : 0u;
+    m.always = top >= 256u;
+    return m;
+}
+
+// lt = (X < top), eq = (X == top) for 32 sites at once, X given as bit-planes
+// X[0] (LSB) .. X[7].  lt is the borrow out of X - top, propagated from the
+// least significant plane: borrow' = maj(~X_k, top_k, borrow); one bitop3 per
+// plane for each of lt and eq.
+__device__ __forceinline__ void compare_planes(const uint32_t (&X)[8], const TopMask &t, uint32_t &lt, uint32_t &eq)
+{
+    uint32_t b = 0u, e = ~0u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        b = MCS_BOP3(X[k], t.tk[k], b, (~MCS_A & MCS_B) | (~MCS_A & MCS_C) | (MCS_B & MCS_C));
+        e = MCS_BOP3(e, X[k], t.tk[k], MCS_A & ~(MCS_B ^ MCS_C));
     }
+    lt = t.always ? ~0u : b;
+    eq = t.always ? 0u : e;
 }
 
 template <int K, bool MEASURE>
@@ -74,7 +89,7 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
     extern __shared__ uint32_t lds[];
     __shared__ long long red[2][16];
     __shared__ uint32_t q_j[kTieQueue], q_meta[kTieQueue];
-    __shared__ uint32_t q_cnt[2];
+    __shared__ uint32_t q_cnt[16];  // items queued by each wave in this half-sweep
     const int l = blockIdx.y;
     const int y0 = blockIdx.x * a.H;
     const int Hh = min(a.H, a.Ly - y0);
@@ -88,6 +103,7 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
     const uint32_t rep = a.replica0 + (uint32_t)l;
     const Thr t4 = a.t4[a.per_lattice ? l : 0];
     const Thr t8 = a.t8[a.per_lattice ? l : 0];
+    const TopMask m4 = top_mask(t4.top), m8 = top_mask(t8.top);
     // thread -> (word column, first row, row stride); no division in the loops
     int P, Q, w0, r0;
     if (Wd <= nt) {
@@ -109,7 +125,11 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
         while (y >= a.Ly) y -= a.Ly;
         return y;
     };
-    if (tid < 2) q_cnt[tid] = 0;
+    // tie queue: wave w owns items [w * wq_cap, (w + 1) * wq_cap); its fill
+    // level wq_n is wave-uniform
+    const int wave = tid >> 6, nwaves = nt >> 6;
+    const uint32_t wq_cap = (uint32_t)(kTieQueue / nwaves), wq_base = (uint32_t)wave * wq_cap;
+    uint32_t wq_n = 0;
 
     // ---- load rows y0-R .. y0+Hh+R-1 and pack: sign bit of each byte,
     // even-x sites to array 0, odd-x sites to array 1.
@@ -147,7 +167,6 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
             const int r_lo = p + 1, r_hi = rows - p - 1;
             const uint32_t w3 = ctr_w3(kTagSweep, (uint32_t)c, sweep);
             const uint32_t w3lo = ctr_w3(kTagSweepLo, (uint32_t)c, sweep);
-            uint32_t *qc = &q_cnt[p & 1];
             for (int r = r_lo + r0; r < r_hi; r += Q) {
                 const int y = lat_row(r);
                 const int q = (c + y) & 1;
@@ -158,9 +177,12 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
                     const uint32_t S = lds[ws];
                     const uint32_t U = lds[widx(r - 1, q, w)], D = lds[widx(r + 1, q, w)];
                     const uint32_t O = lds[widx(r, 1 - q, w)];
-                    uint32_t Sh;
-                    if (q == 0) Sh = __builtin_amdgcn_alignbit(O, lds[widx(r, 1, w == 0 ? Wd - 1 : w - 1)], 31);
-                    else Sh = __builtin_amdgcn_alignbit(lds[widx(r, 0, w + 1 == Wd ? 0 : w + 1)], O, 1);
+                    // even sites: left neighbours are the odd sites one to the
+                    // left (carry from the previous odd word); odd sites: right
+                    // neighbours are the even sites one to the right
+                    const int wl = w == 0 ? Wd - 1 : w - 1, wr = w + 1 == Wd ? 0 : w + 1;
+                    const uint32_t Ol = lds[widx(r, 1, wl)], Er = lds[widx(r, 0, wr)];
+                    const uint32_t Sh = q == 0 ? __builtin_amdgcn_alignbit(O, Ol, 31) : __builtin_amdgcn_alignbit(Er, O, 1);
                     const uint32_t u1 = S ^ U, u2 = S ^ D, u3 = S ^ O, u4 = S ^ Sh;
                     const uint32_t t1 = u1 | u2, t2 = u3 | u4;
                     // at least two of four anti-aligned neighbours: dE <= 0
@@ -176,23 +198,34 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
 #pragma unroll
                     for (int k = 0; k < 8; ++k) X[k] = plane_pair(A, B, k);
                     uint32_t lt8, eq8, lt4, eq4;
-                    compare_planes(X, t8.top, lt8, eq8);
-                    compare_planes(X, t4.top, lt4, eq4);
+                    compare_planes(X, m8, lt8, eq8);
+                    compare_planes(X, m4, lt4, eq4);
                     uint32_t acc = MCS_BOP3(ge2, c8, lt8, MCS_A | (MCS_B & MCS_C)) | (c4 & lt4);
                     uint32_t pend = (c8 & eq8) | (c4 & eq4);
-                    while (pend) {
-                        const int b = __builtin_ctz(pend);
-                        pend &= pend - 1u;
-                        const uint32_t cls8 = (c8 >> b) & 1u;
-                        const uint32_t slot = atomicAdd(qc, 1u);
-                        if (slot < (uint32_t)kTieQueue) {
-                            q_j[slot] = 16u * blk + (uint32_t)b;
-                            q_meta[slot] = (uint32_t)ws | ((uint32_t)b << 16) | (cls8 << 21) | ((uint32_t)interior << 22);
-                        } else {
-                            const uint4 lo = philox(make_uint4(16u * blk + (uint32_t)b, rep, (uint32_t)sweep, w3lo),
-                                                    a.seed_lo, a.seed_hi);
-                            if ((lo.x & 0xFFFFFFu) < (cls8 ? t8.low : t4.low)) acc |= 1u << b;
+                    // append ties to this wave's queue segment: one item per
+                    // pending lane per round, offsets from ballot + mbcnt
+                    uint64_t m = __ballot(pend != 0u);
+                    while (m) {
+                        const uint32_t off = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        if (pend) {
+                            const int b = __builtin_ctz(pend);
+                            pend &= pend - 1u;
+                            const uint32_t cls8 = (c8 >> b) & 1u;
+                            const uint32_t pos = wq_n + off;
+                            if (pos < wq_cap) {
+                                q_j[wq_base + pos] = 16u * blk + (uint32_t)b;
+                                q_meta[wq_base + pos] =
+                                    (uint32_t)ws | ((uint32_t)b << 16) | (cls8 << 21) | ((uint32_t)interior << 22);
+                            } else {
+                                const uint4 lo = philox(
+                                    make_uint4(16u * blk + (uint32_t)b, rep, (uint32_t)sweep, w3lo), a.seed_lo,
+                                    a.seed_hi);
+                                if ((lo.x & 0xFFFFFFu) < (cls8 ? t8.low : t4.low)) acc |= 1u << b;
+                            }
                         }
+                        wq_n = min(wq_cap, wq_n + (uint32_t)__popcll(m));
+                        m = __ballot(pend != 0u);
                     }
                     lds[ws] = S ^ acc;
                     if (interior)
@@ -201,12 +234,22 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
                                  128;
                 }
             }
+            // lanes that left the row loop early hold an older (smaller) fill
+            // level; the lanes that ran longest hold the final one
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) wq_n = max(wq_n, (uint32_t)__shfl_xor((int)wq_n, off, 64));
+            if ((tid & 63) == 0) q_cnt[wave] = wq_n;
             __syncthreads();
-            // settle the queued ties: low 24 bits of r32 against the threshold
-            const uint32_t nq = min(*qc, (uint32_t)kTieQueue);
-            for (uint32_t i = tid; i < nq; i += nt) {
-                const uint32_t meta = q_meta[i];
-                const uint4 lo = philox(make_uint4(q_j[i], rep, (uint32_t)sweep, w3lo), a.seed_lo, a.seed_hi);
+            // settle the queued ties: low 24 bits of r32 against the threshold;
+            // item i of the concatenated segments goes to thread i (mod nt)
+            uint32_t total = 0;
+            for (int sg = 0; sg < nwaves; ++sg) total += q_cnt[sg];
+            for (uint32_t i = tid; i < total; i += nt) {
+                uint32_t sg = 0, k = i;
+                while (k >= q_cnt[sg]) k -= q_cnt[sg++];
+                const uint32_t item = sg * wq_cap + k;
+                const uint32_t meta = q_meta[item];
+                const uint4 lo = philox(make_uint4(q_j[item], rep, (uint32_t)sweep, w3lo), a.seed_lo, a.seed_hi);
                 const bool cls8 = (meta >> 21) & 1u;
                 if ((lo.x & 0xFFFFFFu) < (cls8 ? t8.low : t4.low)) {
                     atomicXor(&lds[meta & 0xFFFFu], 1u << ((meta >> 16) & 31u));
@@ -214,7 +257,7 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
                 }
             }
             __syncthreads();
-            if (tid == 0) *qc = 0;
+            wq_n = 0;
         }
         if (MEASURE) {
             long long m_acc = 0;

@@ -59,6 +59,15 @@ def test_fused_matches_oracle(ctx, shape, plan, nsweeps):
     assert np.array_equal(gem, oem)
 
 
+def test_fused_tie_queue_overflow(ctx):
+    # one wave per band of 56 rows of 8192 sites: ~600 threshold ties per
+    # half-sweep, more than the 512-item tie queue, so some are drawn in place
+    shape = (8192, 112)
+    gs, gem = _gpu_run(ctx, shape, 0.44, 5, 4, 0, 1, 0, (56, 2, 64))
+    os_, oem = _oracle_run(shape, 0.44, 5, 4, 0, 1, 0)
+    assert np.array_equal(gs, os_) and np.array_equal(gem, oem)
+
+
 @pytest.mark.parametrize("beta", [0.0, 0.2, 0.5, 3.0])
 def test_fused_betas(ctx, beta):
     gs, gem = _gpu_run(ctx, (128, 64), beta, 4, 6, 0, 1, 0, (8, 2, 256))
