@@ -156,6 +156,53 @@ int mc_get_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t *H, int32_t *K, i
 int mc_tune_sweep(mc_ctx *ctx, const mc_geom *geom, void *scratch_a, void *scratch_b, double beta,
                   int32_t sweeps, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Population annealing (Sec. "Population annealing", Eq. Q) of npop
+ * populations of R replicas of the 2D L x L ferromagnet (J = 1), one
+ * population per extent L[p], all advanced together.
+ *   Step i (beta_{i-1} -> beta_i): weights w_j = exp(-(beta_i - beta_{i-1})
+ *   (E_j + 2N)) (FP64 host table per step, shifted so w <= 1); C = inclusive
+ *   prefix sum of w in the fixed order: blocks of 64 by doubling steps
+ *   x_i += x_{i-d} (d = 1, 2, .., 32), block totals 64 at a time the same way,
+ *   group totals in sequence, C_i = x_i + (G + B); C_total = C_{R-1};
+ *   ln Q_i = log(C_total / R) + 2N dbeta; multinomial resampling at fixed R:
+ *   slot k draws u_k (53 bits from Philox(ctr = (k, p, i, TAG_RESAMPLE<<24)),
+ *   words 0 and 1), parent = first j whose running maximum of C exceeds
+ *   u_k C_total; copies of parent j fill slots [P_j, P_j + n_j) (P = exclusive
+ *   prefix sum of the copy numbers n); then theta Metropolis sweeps at beta_i
+ *   with replica id p R + slot and sweep numbers (i-1) theta + t.
+ * A fresh anneal (step_first = 1) starts from R independent hot starts
+ * (replica ids p R + k, the exact beta_0 = 0 equilibrium); a later
+ * step_first continues from the population in pop_spins.
+ * L[p] in {4, 8, 16, 32, 64} or a multiple of 64 up to 512; R <= 65536;
+ * npop <= 8.                                                                */
+typedef struct {
+    int32_t npop;
+    const int32_t *L;     /* host [npop]                                       */
+    int32_t R;            /* replicas per population                           */
+    int32_t theta;        /* Metropolis sweeps per step                        */
+    uint64_t seed;
+    int32_t step_first;   /* number of the first step of this call (>= 1)      */
+    int32_t nsteps;       /* steps in this call                                */
+    const double *beta;   /* host [step_first + nsteps]: beta[0..] schedule    */
+} mc_pa_args;
+
+size_t mc_pa_workspace_bytes(const mc_pa_args *args);
+
+/* pop_spins: host array of npop device pointers, each to 2 R L^2 int8: the
+ *   current population in the first R L^2 bytes (input when step_first > 1,
+ *   output always), the second half is scratch.
+ * Ctot, lnQ: host [npop][nsteps].  lnZ: host [npop][nsteps + 1]; lnZ[p][0] =
+ *   ln Z at beta[step_first - 1] (set to L^2 ln 2 on a fresh anneal, read as
+ *   given otherwise), lnZ[p][s] = lnZ[p][s-1] + lnQ[p][s-1].
+ * hist: host int64, per population [nsteps + 1][L^2 + 1] (populations one
+ *   after the other): row 0 the population at beta[step_first - 1], row s
+ *   after step step_first + s - 1; column k counts replicas with E = 4k - 2N.
+ * ws: device workspace of mc_pa_workspace_bytes(args).  Blocking: the steps
+ *   run as one captured hipGraph on `stream`, which is synchronised.       */
+int mc_pa_anneal(mc_ctx *ctx, const mc_pa_args *args, void *const *pop_spins, double *Ctot, double *lnQ,
+                 double *lnZ, int64_t *hist, void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

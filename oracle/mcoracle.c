@@ -430,6 +430,7 @@ int orc_pa_steps(int L, int R, int pop, int step_first, int nsteps, const double
         lnQ[s] = log(ct / (double)R) + dbeta * (double)(2 * N);
         /* running maximum, then the first index whose value exceeds t */
         for (int64_t j = 1; j < R; ++j) if (C[j] < C[j - 1]) C[j] = C[j - 1];
+        #pragma omp parallel for schedule(static)
         for (int64_t k = 0; k < R; ++k) {
             double u = orc_resample_u(seed, (uint32_t)k, (uint32_t)pop, (uint32_t)i);
             double t = u * ct;

@@ -51,6 +51,12 @@ class Geom(ctypes.Structure):
         return 64 if self.layout == MSC64 else 1
 
 
+class PAArgs(ctypes.Structure):
+    _fields_ = [("npop", ctypes.c_int32), ("L", ctypes.POINTER(ctypes.c_int32)), ("R", ctypes.c_int32),
+                ("theta", ctypes.c_int32), ("seed", ctypes.c_uint64), ("step_first", ctypes.c_int32),
+                ("nsteps", ctypes.c_int32), ("beta", ctypes.POINTER(ctypes.c_double))]
+
+
 class SweepArgs(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int32), ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("replica0", ctypes.c_uint32), ("sweep0", ctypes.c_uint64), ("nsweeps", ctypes.c_int32)]
@@ -84,6 +90,10 @@ _lib_fns = dict(
                                                          _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     mc_tune_sweep=_sig("mc_tune_sweep", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _c.c_double, _c.c_int32,
                                                    _vp]),
+    mc_pa_workspace_bytes=_sig("mc_pa_workspace_bytes", _c.c_size_t, [_c.POINTER(PAArgs)]),
+    mc_pa_anneal=_sig("mc_pa_anneal", _c.c_int, [_vp, _c.POINTER(PAArgs), _c.POINTER(_vp), _c.POINTER(_c.c_double),
+                                                 _c.POINTER(_c.c_double), _c.POINTER(_c.c_double),
+                                                 _c.POINTER(_c.c_int64), _vp, _c.c_size_t, _vp]),
 )
 
 
@@ -187,6 +197,57 @@ class Context:
     def measure(self, geom, spins, EM, J=None):
         return self._check(_lib.mc_measure(self._h, ctypes.byref(geom), _ptr(spins), _ptr(J), _ptr(EM),
                                            _stream(self.device)), "mc_measure")
+
+    # --------------------------------------------------------- population annealing
+    @staticmethod
+    def _pa_args(Ls, R, theta, seed, beta, step_first, nsteps):
+        import numpy as np
+
+        Larr = (ctypes.c_int32 * len(Ls))(*[int(x) for x in Ls])
+        barr = np.ascontiguousarray(beta, dtype=np.float64)
+        a = PAArgs(len(Ls), Larr, R, theta, seed, step_first, nsteps,
+                   barr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return a, (Larr, barr)
+
+    def pa_workspace_bytes(self, Ls, R, theta, beta, step_first=1, nsteps=None):
+        nsteps = len(beta) - step_first if nsteps is None else nsteps
+        a, keep = self._pa_args(Ls, R, theta, 0, beta, step_first, nsteps)
+        return int(_lib.mc_pa_workspace_bytes(ctypes.byref(a)))
+
+    def pa_population_tensors(self, Ls, R):
+        """One device buffer of 2 R L^2 int8 per population (current population
+        in the first half)."""
+        return [torch.empty(2 * R * L * L, dtype=torch.int8, device=self.device) for L in Ls]
+
+    def pa_anneal(self, Ls, R, theta, seed, beta, pops, step_first=1, nsteps=None, lnZ0=None, ws=None):
+        """Run annealing steps step_first .. step_first + nsteps - 1; returns a dict
+        with Ctot, lnQ ([npop][nsteps]), lnZ ([npop][nsteps+1]) and hist (list of
+        [nsteps+1][L^2+1] int64 arrays)."""
+        import numpy as np
+
+        nsteps = len(beta) - step_first if nsteps is None else nsteps
+        a, keep = self._pa_args(Ls, R, theta, seed, beta, step_first, nsteps)
+        need = int(_lib.mc_pa_workspace_bytes(ctypes.byref(a)))
+        if ws is None:
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=self.device)
+        npop = len(Ls)
+        ptrs = (_vp * npop)(*[_vp(t.data_ptr()) for t in pops])
+        Ctot = np.zeros((npop, max(nsteps, 1)), dtype=np.float64)
+        lnQ = np.zeros((npop, max(nsteps, 1)), dtype=np.float64)
+        lnZ = np.zeros((npop, nsteps + 1), dtype=np.float64)
+        if lnZ0 is not None:
+            lnZ[:, 0] = lnZ0
+        hist = np.zeros(sum((nsteps + 1) * (L * L + 1) for L in Ls), dtype=np.int64)
+        dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self._check(_lib.mc_pa_anneal(self._h, ctypes.byref(a), ptrs, dp(Ctot), dp(lnQ), dp(lnZ),
+                                      hist.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _ptr(ws),
+                                      ws.numel() * ws.element_size(), _stream(self.device)), "mc_pa_anneal")
+        out, off = [], 0
+        for L in Ls:
+            n = (nsteps + 1) * (L * L + 1)
+            out.append(hist[off:off + n].reshape(nsteps + 1, L * L + 1))
+            off += n
+        return dict(Ctot=Ctot[:, :nsteps], lnQ=lnQ[:, :nsteps], lnZ=lnZ, hist=out)
 
     def set_tile_plan(self, geom, H, K, threads):
         return self._check(_lib.mc_set_tile_plan(self._h, ctypes.byref(geom), H, K, threads), "mc_set_tile_plan")

@@ -42,6 +42,19 @@ int set_device(mc_ctx *ctx)
     return device_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
 }
 
+int capture_stream(mc_ctx *ctx, hipStream_t *out)
+{
+    if (!ctx->capture) {
+        hipError_t e = hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            ctx->capture = nullptr;
+            return device_check(ctx, e, "hipStreamCreateWithFlags");
+        }
+    }
+    *out = ctx->capture;
+    return MC_OK;
+}
+
 int check_geom(mc_ctx *ctx, const mc_geom *g, bool need_count)
 {
     if (!g) return fail(ctx, MC_E_INVAL, "geom is NULL");

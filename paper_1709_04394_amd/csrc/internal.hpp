@@ -27,6 +27,13 @@ struct mc_ctx {
     std::string last_error;
     // tuned launch shapes keyed by (Lx, Ly, count)
     std::map<std::tuple<int, int, int>, mcs::TilePlan> tile_plans;
+    // stream on which launch sequences are recorded into hipGraphs (created
+    // on first use, default priority, destroyed with the context)
+    hipStream_t capture = nullptr;
+    ~mc_ctx()
+    {
+        if (capture) (void)hipStreamDestroy(capture);
+    }
 };
 
 namespace mcs {
@@ -34,6 +41,7 @@ namespace mcs {
 int fail(mc_ctx *ctx, int code, const char *fmt, ...);
 int device_check(mc_ctx *ctx, hipError_t e, const char *what);
 int set_device(mc_ctx *ctx);
+int capture_stream(mc_ctx *ctx, hipStream_t *out);
 int check_geom(mc_ctx *ctx, const mc_geom *g, bool need_count);
 Geom to_geom(const mc_geom *g);
 SweepTables build_tables(double beta);

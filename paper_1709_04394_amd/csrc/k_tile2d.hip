@@ -50,39 +50,6 @@ struct Tile2DArgs {
     int64_t em_sweep0;              // index of this launch's first sweep within EM
 };
 
-// Bit masks of a threshold's top byte: tk[k] = all ones iff bit k of top is
-// set (wave-uniform, lives in scalar registers); top = 256 (T = 2^32) is the
-// "always" case.
-struct TopMask {
-    uint32_t tk[8];
-    bool always;
-};
-
-__device__ __forceinline__ TopMask top_mask(uint32_t top)
-{
-    TopMask m;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) m.tk[k] = ((top >> k) & 1u) ? ~0u : 0u;
-    m.always = top >= 256u;
-    return m;
-}
-
-// lt = (X < top), eq = (X == top) for 32 sites at once, X given as bit-planes
-// X[0] (LSB) .. X[7].  lt is the borrow out of X - top, propagated from the
-// least significant plane: borrow' = maj(~X_k, top_k, borrow); one bitop3 per
-// plane for each of lt and eq.
-__device__ __forceinline__ void compare_planes(const uint32_t (&X)[8], const TopMask &t, uint32_t &lt, uint32_t &eq)
-{
-    uint32_t b = 0u, e = ~0u;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        b = MCS_BOP3(X[k], t.tk[k], b, (~MCS_A & MCS_B) | (~MCS_A & MCS_C) | (MCS_B & MCS_C));
-        e = MCS_BOP3(e, X[k], t.tk[k], MCS_A & ~(MCS_B ^ MCS_C));
-    }
-    lt = t.always ? ~0u : b;
-    eq = t.always ? 0u : e;
-}
-
 template <int K, bool MEASURE>
 __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
 {

@@ -1,0 +1,242 @@
+// pa_driver.hip -- mc_pa_anneal: host side of population annealing.
+// Weight tables (FP64, libm exp, once per step), the per-step launch sequence
+// captured in one hipGraph, and ln Q / ln Z from the device's C_total.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+#include "pa.hpp"
+
+using namespace mcs;
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct PaLayout {
+    size_t wtab = 0, total = 0;
+    std::vector<size_t> E, Enew, x, cmax, n, newparent, ctot, hist;
+};
+
+bool pa_L_ok(int L)
+{
+    if (L < 4 || (L & 1)) return false;
+    if (L <= 64) return (L & (L - 1)) == 0 || L == 64;  // 4, 8, 16, 32, 64
+    return L % 64 == 0 && L <= 512;
+}
+
+PaLayout pa_layout(const mc_pa_args *a)
+{
+    PaLayout lay;
+    int nmax = 0;
+    for (int p = 0; p < a->npop; ++p) nmax = std::max(nmax, a->L[p] * a->L[p]);
+    size_t off = 0;
+    lay.wtab = off;
+    off += align256((size_t)a->nsteps * (size_t)(nmax + 1) * 8);
+    for (int p = 0; p < a->npop; ++p) {
+        const size_t R = (size_t)a->R, N = (size_t)a->L[p] * a->L[p];
+        lay.E.push_back(off), off += align256(R * 4);
+        lay.Enew.push_back(off), off += align256(R * 4);
+        lay.x.push_back(off), off += align256(R * 8);
+        lay.cmax.push_back(off), off += align256(R * 8);
+        lay.n.push_back(off), off += align256(R * 4);
+        lay.newparent.push_back(off), off += align256(R * 4);
+        lay.ctot.push_back(off), off += align256((size_t)std::max(1, a->nsteps) * 8);
+        lay.hist.push_back(off), off += align256((size_t)(a->nsteps + 1) * (N + 1) * 8);
+    }
+    lay.total = off;
+    return lay;
+}
+
+int check_pa(mc_ctx *ctx, const mc_pa_args *a)
+{
+    if (!a) return fail(ctx, MC_E_INVAL, "args is NULL");
+    if (a->npop < 1 || a->npop > kPaMaxPops) return fail(ctx, MC_E_RANGE, "npop must be 1..%d", kPaMaxPops);
+    if (!a->L || !a->beta) return fail(ctx, MC_E_INVAL, "L or beta is NULL");
+    for (int p = 0; p < a->npop; ++p)
+        if (!pa_L_ok(a->L[p]))
+            return fail(ctx, MC_E_SHAPE, "L=%d: population annealing takes L in {4,8,16,32,64} or a multiple of 64 up to 512",
+                        a->L[p]);
+    if (a->R < 1 || a->R > 64 * kPaMaxChunks) return fail(ctx, MC_E_RANGE, "R must be 1..%d", 64 * kPaMaxChunks);
+    if ((int64_t)a->npop * a->R > 4294967295ll) return fail(ctx, MC_E_RANGE, "replica ids exceed 32 bits");
+    if (a->theta < 0 || a->nsteps < 0 || a->step_first < 1) return fail(ctx, MC_E_RANGE, "theta, nsteps or step_first");
+    for (int i = 0; i < a->step_first + a->nsteps; ++i)
+        if (!(a->beta[i] >= 0.0) || std::isinf(a->beta[i])) return fail(ctx, MC_E_RANGE, "beta[%d] out of range", i);
+    for (int i = std::max(1, a->step_first); i < a->step_first + a->nsteps; ++i) {
+        const double db = a->beta[i] - a->beta[i - 1];
+        int nmax = 0;
+        for (int p = 0; p < a->npop; ++p) nmax = std::max(nmax, a->L[p] * a->L[p]);
+        if (!(db >= 0.0) || db * 4.0 * nmax > 700.0)
+            return fail(ctx, MC_E_RANGE, "step %d: beta must not decrease and dbeta * 4N must stay below 700", i);
+    }
+    return MC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mc_pa_workspace_bytes(const mc_pa_args *args)
+{
+    if (check_pa(nullptr, args) != MC_OK) return 0;
+    return pa_layout(args).total;
+}
+
+int mc_pa_anneal(mc_ctx *ctx, const mc_pa_args *a, void *const *pop_spins, double *Ctot, double *lnQ, double *lnZ,
+                 int64_t *hist, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx) return MC_E_INVAL;
+    int rc = check_pa(ctx, a);
+    if (rc) return rc;
+    if (!pop_spins || !hist || !lnZ || (a->nsteps > 0 && (!Ctot || !lnQ)))
+        return fail(ctx, MC_E_INVAL, "an output pointer is NULL");
+    for (int p = 0; p < a->npop; ++p)
+        if (!pop_spins[p]) return fail(ctx, MC_E_INVAL, "pop_spins[%d] is NULL", p);
+    const PaLayout lay = pa_layout(a);
+    if (!ws || ws_bytes < lay.total) return fail(ctx, MC_E_WORKSPACE, "workspace needs %zu bytes", lay.total);
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t s = (hipStream_t)stream, s_cap = nullptr;
+    char *w = (char *)ws;
+    int nmax = 0;
+    for (int p = 0; p < a->npop; ++p) nmax = std::max(nmax, a->L[p] * a->L[p]);
+
+    // host FP64 weight tables: w_i(k) = exp(-(beta_i - beta_{i-1}) 4k)
+    std::vector<double> wt((size_t)a->nsteps * (nmax + 1));
+    for (int s_ = 0; s_ < a->nsteps; ++s_) {
+        const int i = a->step_first + s_;
+        const double dbeta = a->beta[i] - a->beta[i - 1];
+        for (int k = 0; k <= nmax; ++k) wt[(size_t)s_ * (nmax + 1) + k] = std::exp(-dbeta * (double)(4 * k));
+    }
+    hipError_t e = hipSuccess;
+    if (!wt.empty()) e = hipMemcpyAsync(w + lay.wtab, wt.data(), wt.size() * 8, hipMemcpyHostToDevice, s);
+
+    // population layout and launch shape
+    PaStep st{};
+    st.npop = a->npop;
+    st.seed_lo = (uint32_t)a->seed;
+    st.seed_hi = (uint32_t)(a->seed >> 32);
+    st.theta = a->theta;
+    int blocks = 0;
+    for (int p = 0; p < a->npop; ++p) {
+        PaPop &P = st.pop[p];
+        P.L = a->L[p];
+        P.N = P.L * P.L;
+        P.R = a->R;
+        P.Wb = std::min(32, P.L / 2);
+        P.nwr = P.L >= 64 ? P.L / 64 : 1;
+        P.G = std::max(1, std::min(64, 256 / (P.L * P.nwr)));
+        P.blk0 = blocks;
+        blocks += (P.R + P.G - 1) / P.G;
+        P.x = (double *)(w + lay.x[p]);
+        P.cmax = (double *)(w + lay.cmax[p]);
+        P.n = (int32_t *)(w + lay.n[p]);
+        P.newparent = (int32_t *)(w + lay.newparent[p]);
+        P.ctot = (double *)(w + lay.ctot[p]);
+        P.hist = (int64_t *)(w + lay.hist[p]);
+        if (e == hipSuccess) e = launch_fill_i64(P.hist, (int64_t)(a->nsteps + 1) * (P.N + 1), 0, s);
+    }
+    if (e == hipSuccess && a->step_first == 1)
+        for (int p = 0; p < a->npop && e == hipSuccess; ++p) {
+            Geom g{2, a->L[p], a->L[p], 1, (int64_t)a->L[p] * a->L[p], a->R};
+            e = launch_init_int8(g, (int8_t *)pop_spins[p], 1, a->seed, (uint32_t)(p * a->R), s);
+        }
+    if (e != hipSuccess) return device_check(ctx, e, "mc_pa_anneal setup");
+
+    // capture the measuring pass and every step in one graph; the caller's
+    // stream may be the legacy default stream, which cannot be captured, so
+    // the kernels are recorded on the context's own capture stream and the
+    // graph is launched on the caller's stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if ((rc = capture_stream(ctx, &s_cap))) return rc;
+    hipStream_t s_rec = s;
+    s = s_cap;
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    int half = 0;  // which half of each population buffer holds the current population
+    auto bind = [&](PaStep &x) {
+        for (int p = 0; p < a->npop; ++p) {
+            PaPop &P = x.pop[p];
+            int8_t *base = (int8_t *)pop_spins[p];
+            const size_t bytes = (size_t)P.R * P.N;
+            P.cur = base + (half ? bytes : 0);
+            P.nxt = base + (half ? 0 : bytes);
+            P.E = (const int32_t *)(w + (half ? lay.Enew[p] : lay.E[p]));
+            P.Enew = (int32_t *)(w + (half ? lay.E[p] : lay.Enew[p]));
+        }
+    };
+    if (e == hipSuccess) {
+        PaStep m = st;
+        bind(m);
+        m.identity = 1;
+        m.theta = 0;
+        m.step = (uint32_t)a->step_first;  // unused without sweeps
+        m.hist_idx = 0;
+        m.ctot_idx = 0;
+        m.wtab = (const double *)(w + lay.wtab);
+        const SweepTables t = build_tables(0.0);
+        m.t4 = t.met[1];
+        m.t8 = t.met[2];
+        e = launch_pa_step(m, a->R, blocks, s);
+        half ^= 1;
+    }
+    for (int s_ = 0; s_ < a->nsteps && e == hipSuccess; ++s_) {
+        const int i = a->step_first + s_;
+        PaStep x = st;
+        bind(x);
+        x.identity = 0;
+        x.step = (uint32_t)i;
+        x.hist_idx = s_ + 1;
+        x.ctot_idx = s_;
+        x.wtab = (const double *)(w + lay.wtab) + (size_t)s_ * (nmax + 1);
+        const SweepTables t = build_tables(a->beta[i]);
+        x.t4 = t.met[1];
+        x.t8 = t.met[2];
+        e = launch_pa_step(x, a->R, blocks, s);
+        half ^= 1;
+    }
+    hipError_t ec = hipStreamEndCapture(s, &graph);
+    s = s_rec;
+    if (e == hipSuccess) e = ec;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, s);
+    // the final population goes back to the first half of each buffer
+    if (e == hipSuccess && half)
+        for (int p = 0; p < a->npop && e == hipSuccess; ++p) {
+            const size_t bytes = (size_t)a->R * a->L[p] * a->L[p];
+            e = hipMemcpyAsync(pop_spins[p], (int8_t *)pop_spins[p] + bytes, bytes, hipMemcpyDeviceToDevice, s);
+        }
+    // results to the host
+    size_t hoff = 0;
+    for (int p = 0; p < a->npop && e == hipSuccess; ++p) {
+        const size_t N = (size_t)a->L[p] * a->L[p];
+        e = hipMemcpyAsync(hist + hoff, w + lay.hist[p], (size_t)(a->nsteps + 1) * (N + 1) * 8, hipMemcpyDeviceToHost, s);
+        hoff += (size_t)(a->nsteps + 1) * (N + 1);
+        if (e == hipSuccess && a->nsteps > 0)
+            e = hipMemcpyAsync(Ctot + (size_t)p * a->nsteps, w + lay.ctot[p], (size_t)a->nsteps * 8,
+                               hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    if (e != hipSuccess) return device_check(ctx, e, "mc_pa_anneal");
+
+    // ln Q_i = log(C_total / R) + 2N dbeta_i;  ln Z_i = ln Z_{i-1} + ln Q_i,
+    // ln Z(beta_0 = 0) = N ln 2 on a fresh anneal, else lnZ[p][0] as given
+    for (int p = 0; p < a->npop; ++p) {
+        const int N = a->L[p] * a->L[p];
+        double *z = lnZ + (size_t)p * (a->nsteps + 1);
+        if (a->step_first == 1) z[0] = (double)N * std::log(2.0);
+        for (int s_ = 0; s_ < a->nsteps; ++s_) {
+            const int i = a->step_first + s_;
+            const double dbeta = a->beta[i] - a->beta[i - 1];
+            const double c = Ctot[(size_t)p * a->nsteps + s_];
+            const double q = std::log(c / (double)a->R) + dbeta * (double)(2 * N);
+            lnQ[(size_t)p * a->nsteps + s_] = q;
+            z[s_ + 1] = z[s_] + q;
+        }
+    }
+    return MC_OK;
+}
+
+}  // extern "C"
