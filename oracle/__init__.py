@@ -58,6 +58,9 @@ def lib():
         L.orc_draw32.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                  ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32]
         L.orc_draw32.restype = ctypes.c_uint32
+        L.orc_draw_word.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                    ctypes.c_uint64]
+        L.orc_draw_word.restype = ctypes.c_uint32
         L.orc_resample_u.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
         L.orc_resample_u.restype = ctypes.c_double
         L.orc_metropolis_table.argtypes = [ctypes.c_double, ctypes.c_int, u8p]
@@ -108,6 +111,10 @@ def draw_byte(seed, tag, j, replica, sweep, phase):
 
 def draw32(seed, tag, tag_lo, j, replica, sweep, phase):
     return int(lib().orc_draw32(seed, tag, tag_lo, j, replica, sweep, phase))
+
+
+def draw_word(seed, tag, j, replica, sweep):
+    return int(lib().orc_draw_word(seed, tag, j, replica, sweep))
 
 
 def resample_u(seed, k, pop, step):

@@ -120,6 +120,15 @@ uint32_t orc_draw32(uint64_t seed, uint32_t tag, uint32_t tag_lo, uint32_t j,
     return (top << 24) | (out[0] & 0xFFFFFFu);
 }
 
+/* Whole 32-bit draw for item j of a sequential chain (the multicanonical
+ * walkers): word (j mod 4) of Philox(tag, a = j div 4).                      */
+uint32_t orc_draw_word(uint64_t seed, uint32_t tag, uint32_t j, uint32_t replica, uint64_t sweep)
+{
+    uint32_t out[4];
+    orc_block(seed, tag, j >> 2, replica, sweep, 0, out);
+    return out[j & 3u];
+}
+
 /* 53-bit uniform in [0,1) for resampling slot k of population pop at
  * annealing step: words 0 and 1 of one Philox block, 27 + 26 bits.           */
 double orc_resample_u(uint64_t seed, uint32_t k, uint32_t pop, uint32_t step)
@@ -469,7 +478,9 @@ int orc_pa_steps(int L, int R, int pop, int step_first, int nsteps, const double
  * window is rejected and the current energy is counted again.  The histogram
  * receives the level after every attempted move.
  * T[k*4 + d] for d = 0..3 <-> level change -2, -1, +1, +2:
- *   ceil(min(1, exp(lnW[k'] - lnW[k])) 2^32).                                */
+ *   ceil(min(1, exp(lnW[k'] - lnW[k])) 2^32), at least 1.
+ * The update of site i in sweep t of walker w draws the whole 32-bit word
+ * (i mod 4) of Philox(TAG_MUCA, a = i div 4, replica = w, sweep = t).       */
 void orc_muca_table(int L, const double *lnW, uint64_t *T)
 {
     int64_t N = (int64_t)L * L, K = N / 2;
@@ -482,6 +493,7 @@ void orc_muca_table(int L, const double *lnW, uint64_t *T)
                 double x = lnW[k2] - lnW[k];
                 double p = x >= 0.0 ? 1.0 : exp(x);
                 v = (uint64_t)ceil(ldexp(p, 32));
+                if (v == 0) v = 1; /* p below 2^-32 (exp underflow) counts as 2^-32 */
             }
             T[k * 4 + d] = v;
         }
@@ -533,8 +545,7 @@ int orc_muca_sweeps(int L, int walkers, int8_t *spins, int64_t *E, const double 
                     int dE = 2 * s[i] * h;
                     int64_t e2 = e + dE;
                     if (e2 <= 0) {
-                        uint32_t r = orc_draw32(seed, ORC_TAG_MUCA, ORC_TAG_MUCA_LO, (uint32_t)i,
-                                                (uint32_t)w, sweep, 0);
+                        uint32_t r = orc_draw_word(seed, ORC_TAG_MUCA, (uint32_t)i, (uint32_t)w, sweep);
                         int64_t k = (e + 2 * N) / 4;
                         int accept;
                         if (dE == 0) accept = 1;
