@@ -203,6 +203,63 @@ size_t mc_pa_workspace_bytes(const mc_pa_args *args);
 int mc_pa_anneal(mc_ctx *ctx, const mc_pa_args *args, void *const *pop_spins, double *Ctot, double *lnQ,
                  double *lnZ, int64_t *hist, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Multicanonical simulation with parallel walkers (Sec. "Multicanonical
+ * simulations": walkers share W(E); their histograms are added; Eq. muca,
+ * Eq. weight_modification) of the 2D L x L ferromagnet, restricted to the
+ * energy window [-2N, 0] (levels k = (E + 2N)/4 = 0..N/2; g(E) = g(-E)
+ * gives the other half).  Sites are visited in sequential (typewriter) order,
+ * the same order for every walker; a flip is accepted with min(1,
+ * W(E')/W(E)), i.e. r32 < T[k][d] = max(1, ceil(min(1, exp(lnW[k+d] -
+ * lnW[k])) 2^32)) with r32 = word (i mod 4) of Philox(ctr = (i/4, walker,
+ * sweep, TAG_MUCA << 24)); a move out of the window is rejected and the
+ * current level counted again; the histogram counts the level after every
+ * attempted move.  L in {4, 8, 12, 16, 24, 32, 48, 64, 96, 128}.            */
+size_t mc_muca_workspace_bytes(int32_t L, int32_t walkers);
+
+/* Walker start: hot start of walker w keyed by replica id w; if its energy is
+ * above the window the odd sub-lattice is flipped (E -> -E).
+ * spins: device int8 [walkers][L^2]; E: device int64 [walkers].  Stream-ordered. */
+int mc_muca_start(mc_ctx *ctx, int32_t L, int32_t walkers, uint64_t seed, int8_t *spins, int64_t *E, void *stream);
+
+/* nsweeps multicanonical sweeps of every walker at weights lnW (host
+ * [N/2 + 1], finite), sweep numbers sweep0.., updating spins and E in place;
+ * when record is set the visited levels are added to H (device int64
+ * [N/2 + 1]).  Blocking (the host table must outlive the upload).          */
+int mc_muca_sweeps(mc_ctx *ctx, int32_t L, int32_t walkers, int8_t *spins, int64_t *E, const double *lnW,
+                   uint64_t seed, uint64_t sweep0, int32_t nsweeps, int32_t record, int64_t *H, void *ws,
+                   size_t ws_bytes, void *stream);
+
+typedef struct {
+    int32_t L, walkers;
+    int32_t eq_sweeps;    /* unrecorded sweeps at the start of each iteration   */
+    int32_t rec_sweeps;   /* recorded sweeps per iteration                      */
+    int32_t max_iter;     /* weight iterations allowed                          */
+    int32_t prod_sweeps;  /* production sweeps at the final weights             */
+    double flat;          /* flatness criterion min/max over reachable levels   */
+    uint64_t seed;
+} mc_muca_args;
+
+typedef struct {
+    int32_t iterations, converged;
+    int64_t sweeps_per_walker;  /* eq + rec sweeps of all iterations          */
+    double min_over_max;        /* flatness of the last iteration             */
+} mc_muca_stats;
+
+/* The whole method: walker start, iterations of eq_sweeps + rec_sweeps with
+ * the plain recursion ln W -= ln H (H > 0; then ln W at E = 0 set to 0) until
+ * min/max of H over all window levels but k = 1 reaches flat, then
+ * prod_sweeps at fixed weights; ln g = ln H_prod - ln W (-inf where empty).
+ * lnW_init: host [N/2 + 1] initial ln W, or NULL for flat weights.
+ * Outputs on the host: lnW_out, H_out (production), lng_out [N/2 + 1];
+ * flat_out [max_iter] (may be NULL); stats.  spins: device int8
+ * [walkers][L^2] walker lattices on return.  Returns MC_E_NOTCONV (outputs
+ * still written) if max_iter iterations did not give a flat histogram.
+ * Blocking.                                                                 */
+int mc_muca_run(mc_ctx *ctx, const mc_muca_args *args, const double *lnW_init, int8_t *spins, double *lnW_out,
+                int64_t *H_out, double *lng_out, double *flat_out, mc_muca_stats *stats, void *ws, size_t ws_bytes,
+                void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,6 +57,17 @@ class PAArgs(ctypes.Structure):
                 ("nsteps", ctypes.c_int32), ("beta", ctypes.POINTER(ctypes.c_double))]
 
 
+class MucaArgs(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("walkers", ctypes.c_int32), ("eq_sweeps", ctypes.c_int32),
+                ("rec_sweeps", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("prod_sweeps", ctypes.c_int32),
+                ("flat", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class MucaStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("sweeps_per_walker", ctypes.c_int64),
+                ("min_over_max", ctypes.c_double)]
+
+
 class SweepArgs(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int32), ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("replica0", ctypes.c_uint32), ("sweep0", ctypes.c_uint64), ("nsweeps", ctypes.c_int32)]
@@ -90,6 +101,15 @@ _lib_fns = dict(
                                                          _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     mc_tune_sweep=_sig("mc_tune_sweep", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _c.c_double, _c.c_int32,
                                                    _vp]),
+    mc_muca_workspace_bytes=_sig("mc_muca_workspace_bytes", _c.c_size_t, [_c.c_int32, _c.c_int32]),
+    mc_muca_start=_sig("mc_muca_start", _c.c_int, [_vp, _c.c_int32, _c.c_int32, _c.c_uint64, _vp, _vp, _vp]),
+    mc_muca_sweeps=_sig("mc_muca_sweeps", _c.c_int, [_vp, _c.c_int32, _c.c_int32, _vp, _vp, _c.POINTER(_c.c_double),
+                                                     _c.c_uint64, _c.c_uint64, _c.c_int32, _c.c_int32, _vp, _vp,
+                                                     _c.c_size_t, _vp]),
+    mc_muca_run=_sig("mc_muca_run", _c.c_int, [_vp, _c.POINTER(MucaArgs), _c.POINTER(_c.c_double), _vp,
+                                               _c.POINTER(_c.c_double), _c.POINTER(_c.c_int64),
+                                               _c.POINTER(_c.c_double), _c.POINTER(_c.c_double),
+                                               _c.POINTER(MucaStats), _vp, _c.c_size_t, _vp]),
     mc_pa_workspace_bytes=_sig("mc_pa_workspace_bytes", _c.c_size_t, [_c.POINTER(PAArgs)]),
     mc_pa_anneal=_sig("mc_pa_anneal", _c.c_int, [_vp, _c.POINTER(PAArgs), _c.POINTER(_vp), _c.POINTER(_c.c_double),
                                                  _c.POINTER(_c.c_double), _c.POINTER(_c.c_double),
@@ -248,6 +268,59 @@ class Context:
             out.append(hist[off:off + n].reshape(nsteps + 1, L * L + 1))
             off += n
         return dict(Ctot=Ctot[:, :nsteps], lnQ=lnQ[:, :nsteps], lnZ=lnZ, hist=out)
+
+    # ----------------------------------------------------------- multicanonical
+    def muca_workspace(self, L, walkers):
+        n = int(_lib.mc_muca_workspace_bytes(L, walkers))
+        if n == 0:
+            raise MCError(MC_E_SHAPE, "unsupported L=%d or walkers=%d" % (L, walkers))
+        return torch.empty(n, dtype=torch.uint8, device=self.device)
+
+    def muca_start(self, L, walkers, seed, spins=None, E=None):
+        spins = torch.empty((walkers, L * L), dtype=torch.int8, device=self.device) if spins is None else spins
+        E = torch.empty(walkers, dtype=torch.int64, device=self.device) if E is None else E
+        self._check(_lib.mc_muca_start(self._h, L, walkers, seed, _ptr(spins), _ptr(E), _stream(self.device)),
+                    "mc_muca_start")
+        return spins, E
+
+    def muca_sweeps(self, L, spins, E, lnW, seed, sweep0, nsweeps, record, H=None, ws=None):
+        import numpy as np
+
+        walkers = E.numel()
+        ws = self.muca_workspace(L, walkers) if ws is None else ws
+        lw = np.ascontiguousarray(lnW, dtype=np.float64)
+        self._check(_lib.mc_muca_sweeps(self._h, L, walkers, _ptr(spins), _ptr(E),
+                                        lw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), seed, sweep0, nsweeps,
+                                        1 if record else 0, _ptr(H), _ptr(ws), ws.numel(), _stream(self.device)),
+                    "mc_muca_sweeps")
+
+    def muca_run(self, L, walkers, seed, eq_sweeps, rec_sweeps, max_iter, prod_sweeps, flat=0.8, lnW_init=None,
+                 spins=None, ws=None):
+        """Full multicanonical run; returns a dict like oracle.muca_run."""
+        import numpy as np
+
+        K1 = L * L // 2 + 1
+        spins = torch.empty((walkers, L * L), dtype=torch.int8, device=self.device) if spins is None else spins
+        ws = self.muca_workspace(L, walkers) if ws is None else ws
+        a = MucaArgs(L, walkers, eq_sweeps, rec_sweeps, max_iter, prod_sweeps, float(flat), seed)
+        init = None
+        if lnW_init is not None:
+            init = np.ascontiguousarray(lnW_init, dtype=np.float64)
+        lnW = np.zeros(K1)
+        H = np.zeros(K1, dtype=np.int64)
+        lng = np.zeros(K1)
+        hist = np.zeros(max(1, max_iter))
+        st = MucaStats()
+        dp = lambda x: None if x is None else x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        rc = _lib.mc_muca_run(self._h, ctypes.byref(a), dp(init), _ptr(spins), dp(lnW),
+                              H.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), dp(lng), dp(hist), ctypes.byref(st),
+                              _ptr(ws), ws.numel(), _stream(self.device))
+        if rc not in (MC_OK, MC_E_NOTCONV):
+            self._check(rc, "mc_muca_run")
+        return dict(lnW=lnW, iterations=st.iterations, converged=bool(st.converged),
+                    min_over_max=st.min_over_max, sweeps_per_walker=st.sweeps_per_walker,
+                    H_prod=H if prod_sweeps > 0 else None, lng=lng if prod_sweeps > 0 else None,
+                    history=list(hist[:st.iterations]), spins=spins)
 
     def set_tile_plan(self, geom, H, K, threads):
         return self._check(_lib.mc_set_tile_plan(self._h, ctypes.byref(geom), H, K, threads), "mc_set_tile_plan")

@@ -1,0 +1,218 @@
+// k_muca.hip -- parallel-walker multicanonical sweeps (Sec. "Multicanonical
+// simulations": p walkers share one weight function, their histograms are
+// added; Eq. muca, Eq. weight_modification) for 2D L x L ferromagnets.
+//
+// One lane is one walker; 64 walkers form a wave and visit the same site at
+// the same time (the paper's shared site sequence), each with its own random
+// numbers.  A walker's rows are bit-packed in registers while it sweeps them
+// in sequential (typewriter) order; the rows of the whole lattice stay int8 in
+// global memory and stream through once per sweep.  The acceptance table
+// T[level][direction] (FP64 host values as 32-bit thresholds) sits in LDS
+// (131 KB at L = 128, within gfx950's 160 KB), so the dependent chain of one
+// update is a few bit operations, one LDS read and a compare.  Moves that
+// would leave the energy window [-2N, 0] are rejected and the current level
+// is counted again.
+#include "internal.hpp"
+#include "muca.hpp"
+
+namespace mcs {
+
+// Sign bits of four int8 spins -> 4 bits (bit set <=> -1): bytes' bit 7 to
+// positions 0, 8, 16, 24, then a multiply gathers them at 21..24.
+__device__ __forceinline__ uint32_t pack4(uint32_t d)
+{
+    const uint32_t m = (d & 0x80808080u) >> 7;
+    return (m * 0x00204081u >> 21) & 0xFu;
+}
+
+// 4 bits -> four int8 spins (+1 for 0, -1 for 1).
+__device__ __forceinline__ uint32_t unpack4(uint32_t nib)
+{
+    const uint32_t bits = (nib * 0x00204081u) & 0x01010101u;
+    return __builtin_amdgcn_perm(0u, 0x0000FF01u, bits);
+}
+
+template <int L>
+__device__ __forceinline__ void load_row(const int8_t *sp, int y, uint32_t (&row)[(L + 31) / 32])
+{
+    constexpr int NW = (L + 31) / 32;
+    const uint32_t *p = (const uint32_t *)(sp + y * L);
+#pragma unroll
+    for (int i = 0; i < NW; ++i) row[i] = 0;
+#pragma unroll
+    for (int q = 0; q < L / 4; ++q) row[(4 * q) / 32] |= pack4(p[q]) << ((4 * q) % 32);
+}
+
+template <int L>
+__device__ __forceinline__ void store_row(int8_t *sp, int y, const uint32_t (&row)[(L + 31) / 32])
+{
+    uint32_t *p = (uint32_t *)(sp + y * L);
+#pragma unroll
+    for (int q = 0; q < L / 4; ++q) p[q] = unpack4((row[(4 * q) / 32] >> ((4 * q) % 32)) & 0xFu);
+}
+
+template <int L>
+__device__ __forceinline__ uint32_t bit_at(const uint32_t (&row)[(L + 31) / 32], int x)
+{
+    return (row[x / 32] >> (x % 32)) & 1u;
+}
+
+template <int L>
+__global__ __launch_bounds__(64) void k_muca(MucaArgs a)
+{
+    constexpr int N = L * L, NW = (L + 31) / 32, K = N / 2;
+    extern __shared__ uint32_t tab[];  // [(K + 1) * 4] thresholds minus one
+    const int lane = threadIdx.x;
+    for (int i = lane; i < (K + 1) * 4; i += 64) tab[i] = a.table[i];
+    __syncthreads();
+    const int w = blockIdx.x * 64 + lane;
+    if (w >= a.W) return;
+    int8_t *sp = a.spins + (int64_t)w * N;
+    int k = (int)((a.E[w] + 2 * N) / 4);
+    uint32_t *hist = a.hist + (int64_t)blockIdx.x * (K + 1);
+    for (int t = 0; t < a.nsweeps; ++t) {
+        const uint64_t sweep = a.sweep0 + (uint64_t)t;
+        const uint32_t w3 = ctr_w3(kTagMuca, 0, sweep);
+        uint32_t up[NW], cur[NW], dn[NW], row0[NW];
+        load_row<L>(sp, L - 1, up);
+        load_row<L>(sp, 0, cur);
+        load_row<L>(sp, 1 % L, dn);
+        for (int y = 0; y < L; ++y) {
+            uint4 blk = make_uint4(0, 0, 0, 0);
+#pragma unroll
+            for (int x = 0; x < L; ++x) {
+                if (x % 4 == 0)
+                    blk = philox(make_uint4((uint32_t)(x + L * y) >> 2, (uint32_t)w, (uint32_t)sweep, w3), a.seed_lo,
+                                 a.seed_hi);
+                const uint32_t r = (x % 4 == 0) ? blk.x : (x % 4 == 1) ? blk.y : (x % 4 == 2) ? blk.z : blk.w;
+                const uint32_t s = bit_at<L>(cur, x);
+                const uint32_t nl = bit_at<L>(cur, (x + L - 1) % L), nr = bit_at<L>(cur, (x + 1) % L);
+                const uint32_t nu = bit_at<L>(up, x), nd = bit_at<L>(dn, x);
+                const int anti = (int)((s ^ nl) + (s ^ nr) + (s ^ nu) + (s ^ nd));
+                const int dl = 2 - anti;  // level change if the spin flips (dE = 4 dl)
+                const int k2 = k + dl;
+                bool acc;
+                if (dl == 0) acc = true;
+                else acc = k2 <= K && r <= tab[4 * k + (dl < 0 ? dl + 2 : dl + 1)];
+                if (acc) {
+                    cur[x / 32] ^= 1u << (x % 32);
+                    k = k2;
+                }
+                if (a.record) atomicAdd(&hist[k], 1u);
+            }
+            store_row<L>(sp, y, cur);
+            if (y == 0) {
+#pragma unroll
+                for (int i = 0; i < NW; ++i) row0[i] = cur[i];
+            }
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {
+                up[i] = cur[i];
+                cur[i] = dn[i];
+            }
+            if (y + 2 < L) load_row<L>(sp, y + 2, dn);
+            else {
+#pragma unroll
+                for (int i = 0; i < NW; ++i) dn[i] = row0[i];
+            }
+        }
+    }
+    a.E[w] = 4 * (int64_t)k - 2 * N;
+}
+
+// Walker start: hot start keyed by the walker index (already written by the
+// init kernel), energy, and a flip of the odd sub-lattice when E > 0 (E -> -E).
+__global__ void k_muca_start(int8_t *spins, int64_t *E, int L, int W)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= W) return;
+    const int N = L * L;
+    int8_t *s = spins + (int64_t)w * N;
+    int64_t e = 0;
+    for (int y = 0; y < L; ++y)
+        for (int x = 0; x < L; ++x) {
+            const int si = s[x + L * y];
+            e -= si * (s[(x + 1) % L + L * y] + s[x + L * ((y + 1) % L)]);
+        }
+    if (e > 0) {
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x)
+                if ((x + y) & 1) s[x + L * y] = (int8_t)-s[x + L * y];
+        e = -e;
+    }
+    E[w] = e;
+}
+
+// H[k] += sum over workgroup slices of their counts (fixed order).
+__global__ void k_muca_merge(const uint32_t *slices, int nslices, int nlev, int64_t *H)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nlev) return;
+    int64_t s = 0;
+    for (int b = 0; b < nslices; ++b) s += slices[(int64_t)b * nlev + k];
+    H[k] += s;
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+template <int L>
+static hipError_t launch_muca_L(const MucaArgs &a, hipStream_t s)
+{
+    constexpr int K = L * L / 2;
+    const size_t lds = (size_t)(K + 1) * 4 * 4;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_muca<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_muca<L>, dim3((a.W + 63) / 64), dim3(64), lds, s, a);
+    return hipGetLastError();
+}
+
+bool muca_L_supported(int L)
+{
+    switch (L) {
+    case 4: case 8: case 12: case 16: case 24: case 32: case 48: case 64: case 96: case 128: return true;
+    default: return false;
+    }
+}
+
+hipError_t launch_muca_sweeps(const MucaArgs &a, int L, hipStream_t s)
+{
+    const int nlev = L * L / 2 + 1, nb = (a.W + 63) / 64;
+    if (a.record) hipLaunchKernelGGL(k_fill_u32, dim3(256), dim3(256), 0, s, a.hist, (int64_t)nb * nlev);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (L) {
+    case 4: e = launch_muca_L<4>(a, s); break;
+    case 8: e = launch_muca_L<8>(a, s); break;
+    case 12: e = launch_muca_L<12>(a, s); break;
+    case 16: e = launch_muca_L<16>(a, s); break;
+    case 24: e = launch_muca_L<24>(a, s); break;
+    case 32: e = launch_muca_L<32>(a, s); break;
+    case 48: e = launch_muca_L<48>(a, s); break;
+    case 64: e = launch_muca_L<64>(a, s); break;
+    case 96: e = launch_muca_L<96>(a, s); break;
+    case 128: e = launch_muca_L<128>(a, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    if (a.record) hipLaunchKernelGGL(k_muca_merge, dim3((nlev + 255) / 256), dim3(256), 0, s, a.hist, nb, nlev, a.H);
+    return hipGetLastError();
+}
+
+hipError_t launch_muca_start(int8_t *spins, int64_t *E, int L, int W, uint64_t seed, hipStream_t s)
+{
+    Geom g{2, L, L, 1, (int64_t)L * L, W};
+    hipError_t e = launch_init_int8(g, spins, 1, seed, 0u, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_muca_start, dim3((W + 63) / 64), dim3(64), 0, s, spins, E, L, W);
+    return hipGetLastError();
+}
+
+}  // namespace mcs

@@ -1,0 +1,122 @@
+"""GPU multicanonical walkers against the CPU oracle, through the C ABI.
+
+Bit-exact: walker starts (spins, energies), the walker lattices and energies
+after unrecorded and recorded sweeps at arbitrary weights, the summed
+histograms, and whole runs of the plain weight recursion (iteration count,
+every ln W, the production histogram and ln g).  Walker counts are not
+multiples of 64; L covers every supported extent, including the 4096-walker
+configuration at L = 16 (whole run) and single iterations at L = 64 and 128
+(iteration replay: same ln W and walker state in, same histogram and state out).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import exact
+
+pytestmark = pytest.mark.gpu
+mcs = pytest.importorskip("paper_1709_04394_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return mcs.Context(0)
+
+
+def _weights(L, kind, seed=0):
+    K1 = L * L // 2 + 1
+    N = L * L
+    if kind == "flat":
+        return np.zeros(K1)
+    if kind == "canonical":
+        return np.array([-0.35 * (4 * k - 2 * N) for k in range(K1)])
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.normal(0.0, 1.5, K1))
+
+
+@pytest.mark.parametrize("L,W", [(8, 100), (16, 64), (24, 70), (48, 65)])
+def test_start_parity(ctx, L, W):
+    spins, E = ctx.muca_start(L, W, 19 + L)
+    torch.cuda.synchronize()
+    os_, oE = oracle.muca_start(L, W, 19 + L)
+    assert np.array_equal(spins.cpu().numpy().reshape(-1), os_)
+    assert np.array_equal(E.cpu().numpy(), oE)
+
+
+@pytest.mark.parametrize("L,W,kind,neq,nrec", [(4, 70, "random", 2, 5), (8, 100, "canonical", 3, 4),
+                                               (12, 64, "random", 1, 3), (16, 130, "flat", 2, 3),
+                                               (24, 64, "random", 1, 2), (32, 65, "canonical", 1, 2),
+                                               (48, 64, "random", 1, 1), (64, 64, "flat", 0, 1),
+                                               (96, 64, "random", 0, 1), (128, 64, "canonical", 0, 1)])
+def test_sweeps_parity(ctx, L, W, kind, neq, nrec):
+    seed = 5 + L
+    lnW = _weights(L, kind, seed)
+    spins, E = ctx.muca_start(L, W, seed)
+    H = torch.zeros(L * L // 2 + 1, dtype=torch.int64, device="cuda")
+    ctx.muca_sweeps(L, spins, E, lnW, seed, 0, neq, False)
+    ctx.muca_sweeps(L, spins, E, lnW, seed, neq, nrec, True, H=H)
+    torch.cuda.synchronize()
+    os_, oE = oracle.muca_start(L, W, seed)
+    oracle.muca_sweeps(L, os_, oE, lnW, seed, 0, neq, False)
+    oH = oracle.muca_sweeps(L, os_, oE, lnW, seed, neq, nrec, True)
+    assert np.array_equal(E.cpu().numpy(), oE)
+    assert np.array_equal(H.cpu().numpy(), oH)
+    assert np.array_equal(spins.cpu().numpy().reshape(-1), os_)
+
+
+def _compare_runs(g, o):
+    assert g["iterations"] == o["iterations"] and g["converged"] == o["converged"]
+    assert np.array_equal(g["lnW"], o["lnW"])
+    assert np.array_equal(g["H_prod"], o["H_prod"])
+    assert np.array_equal(g["lng"], o["lng"])
+    assert g["history"] == pytest.approx(o["history"], abs=0, rel=0)
+
+
+def test_run_parity_small(ctx):
+    args = dict(eq_sweeps=2, rec_sweeps=40, max_iter=30, prod_sweeps=200)
+    g = ctx.muca_run(8, 1024, 27, **args)
+    o = oracle.muca_run(8, 1024, 27, **args)
+    _compare_runs(g, o)
+
+
+def test_run_parity_config_L16(ctx):
+    # 4096 walkers, 2 unrecorded + 10 recorded sweeps per iteration
+    args = dict(eq_sweeps=2, rec_sweeps=10, max_iter=40, prod_sweeps=50)
+    g = ctx.muca_run(16, 4096, 19 + 16, **args)
+    o = oracle.muca_run(16, 4096, 19 + 16, **args)
+    _compare_runs(g, o)
+    assert g["converged"]
+
+
+def test_density_of_states_vs_exact_L16(ctx):
+    # a long production run at the converged weights recovers the exact g(E)
+    g = ctx.muca_run(16, 4096, 35, eq_sweeps=2, rec_sweeps=10, max_iter=40, prod_sweeps=4000)
+    assert g["converged"]
+    lng = np.array([exact.big_log(v) if v else -np.inf for v in exact.exact_g(16)[:16 * 16 // 2 + 1]])
+    m = oracle.muca_flat_levels(16)
+    est, ex = g["lng"][m], lng[m]
+    c = np.logaddexp.reduce(ex) - np.logaddexp.reduce(est)
+    assert np.max(np.abs(est + c - ex)) < 0.05, np.max(np.abs(est + c - ex))
+
+
+@pytest.mark.parametrize("L,W", [(64, 4096), (128, 512)])
+def test_iteration_replay_at_scale(ctx, L, W):
+    # one iteration (2 unrecorded + 1 recorded sweeps) from a common state
+    seed = 19 + L
+    lnW = _weights(L, "random", seed)
+    spins, E = ctx.muca_start(L, W, seed)
+    H = torch.zeros(L * L // 2 + 1, dtype=torch.int64, device="cuda")
+    ctx.muca_sweeps(L, spins, E, lnW, seed, 100, 2, False)
+    ctx.muca_sweeps(L, spins, E, lnW, seed, 102, 1, True, H=H)
+    torch.cuda.synchronize()
+    os_, oE = oracle.muca_start(L, W, seed)
+    oracle.muca_sweeps(L, os_, oE, lnW, seed, 100, 2, False)
+    oH = oracle.muca_sweeps(L, os_, oE, lnW, seed, 102, 1, True)
+    assert np.array_equal(E.cpu().numpy(), oE)
+    assert np.array_equal(H.cpu().numpy(), oH)
+    assert np.array_equal(spins.cpu().numpy().reshape(-1), os_)
