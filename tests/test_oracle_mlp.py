@@ -1,0 +1,82 @@
+"""Pins of the FP64 MLP reference.
+
+* The analytic gradient equals central finite differences of the loss
+  (relative error <= 1e-6 on every parameter block);
+* 4417 parameters; Xavier-uniform initial weights lie in +-sqrt(6/(fi+fo))
+  with mean ~ 0 and variance a^2/3; biases start at zero;
+* the first Adam step moves every parameter with non-zero gradient by lr
+  against the sign of its gradient (bias-corrected moments: m^/sqrt(v^) = sign);
+* training on the exact entropy deficit of small lattices lowers the loss.
+"""
+import math
+
+import numpy as np
+
+import oracle
+from oracle import exact
+from oracle import mlp
+
+
+def _data(n=300, seed=0):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1, 1, size=(n, 2))
+    Y = np.sin(2 * X[:, 0]) * 0.3 + 0.2 * X[:, 1] ** 2 - 0.1
+    return X, Y
+
+
+def test_parameter_count_and_init():
+    assert mlp.NPARAMS == 4417
+    p = mlp.init_params(7)
+    q = mlp.unflatten(p)
+    for name, (fo, fi) in (("W1", (64, 2)), ("W2", (64, 64)), ("W3", (1, 64))):
+        a = math.sqrt(6.0 / (fi + fo))
+        w = q[name].reshape(-1)
+        assert np.all(np.abs(w) <= a)
+        if w.size > 100:
+            assert abs(w.mean()) < 4 * a / math.sqrt(3 * w.size)
+            assert abs(w.var() / (a * a / 3.0) - 1.0) < 0.15
+    for name in ("b1", "b2", "b3"):
+        assert np.all(q[name] == 0)
+    assert not np.array_equal(p, mlp.init_params(8))
+
+
+def test_gradient_matches_finite_differences():
+    X, Y = _data()
+    p = mlp.init_params(3)
+    p = p + np.random.default_rng(1).normal(0, 0.05, p.size)  # non-zero biases too
+    loss, g = mlp.loss_and_grad(p, X, Y)
+    rng = np.random.default_rng(2)
+    off = 0
+    for name, shape in mlp.SHAPES:
+        n = int(np.prod(shape))
+        idx = off + rng.choice(n, size=min(n, 12), replace=False)
+        for i in idx:
+            h = 1e-6 * max(1.0, abs(p[i]))
+            pp, pm = p.copy(), p.copy()
+            pp[i] += h
+            pm[i] -= h
+            fd = (mlp.loss_and_grad(pp, X, Y)[0] - mlp.loss_and_grad(pm, X, Y)[0]) / (2 * h)
+            assert abs(fd - g[i]) <= 1e-6 * max(1e-3, np.max(np.abs(g))), (name, i, fd, g[i])
+        off += n
+
+
+def test_first_adam_step_is_sign_times_lr():
+    X, Y = _data()
+    p0 = mlp.init_params(3)
+    _, g = mlp.loss_and_grad(p0, X, Y)
+    p1, _ = mlp.train(p0, X, Y, 1, lr=1e-3)
+    nz = np.abs(g) > 1e-4  # well above eps = 1e-8, so |step| = lr to 1e-4
+    assert nz.sum() > 1000
+    assert np.allclose((p0 - p1)[nz], 1e-3 * np.sign(g[nz]), rtol=2e-4, atol=0)
+
+
+def test_training_on_exact_entropy_lowers_loss():
+    lnW = {}
+    for L in (8, 12, 16):
+        g = exact.exact_g(L)
+        K = L * L // 2
+        lng = np.array([exact.big_log(v) if v else 0.0 for v in g[:K + 1]])
+        lnW[L] = -(lng - lng[K])  # ln W = -ln g, zero at E = 0
+    X, Y = mlp.training_set(lnW)
+    p, losses = mlp.train(mlp.init_params(5), X, Y, 300, lr=3e-3)
+    assert losses[-1] < 0.05 * losses[0]
