@@ -260,6 +260,41 @@ int mc_muca_run(mc_ctx *ctx, const mc_muca_args *args, const double *lnW_init, i
                 int64_t *H_out, double *lng_out, double *flat_out, mc_muca_stats *stats, void *ws, size_t ws_bytes,
                 void *stream);
 
+/* ------------------------------------------------------------------------
+ * A small MLP that predicts initial multicanonical weights from what the
+ * method itself produced at smaller L: x = (E/N + 1, 32/L - 1) -> tanh(64)
+ * -> tanh(64) -> y, FP32, 4417 parameters flattened as W1 [64][2], b1 [64],
+ * W2 [64][64], b2 [64], W3 [1][64], b3 [1]; loss = mean squared error;
+ * full-batch Adam.  The initial ln W of an L x L lattice is -N y(E).
+ * X: device float [n][2]; Y: device float [n]; params: device float [4417]. */
+int32_t mc_mlp_param_count(void);
+size_t mc_mlp_workspace_bytes(int32_t n);
+
+/* Xavier-uniform weights, zero biases: parameter idx draws word (idx mod 4)
+ * of Philox(ctr = (idx / 4, 0, 0, TAG_MLP_INIT << 24)); w = (2u - 1)
+ * sqrt(6 / (fan_in + fan_out)), u = (r >> 8) 2^-24, in FP64 rounded to FP32.
+ * Stream-ordered.                                                          */
+int mc_mlp_init(mc_ctx *ctx, float *params, uint64_t seed, void *stream);
+
+/* Gradient of the loss (device float [4417]) and the loss (device float [1])
+ * at params, summed over 32-sample chunks in chunk order.  Stream-ordered.  */
+int mc_mlp_grad(mc_ctx *ctx, const float *params, const float *X, const float *Y, int32_t n, float *grad, float *loss,
+                void *ws, size_t ws_bytes, void *stream);
+
+typedef struct {
+    int32_t epochs;
+    float lr, beta1, beta2, eps;  /* Adam; 1e-3, 0.9, 0.999, 1e-8 as usual */
+} mc_mlp_args;
+
+/* epochs full-batch Adam steps on params (in/out); loss_log: device float
+ * [epochs], the loss before each step.  All epochs run as one captured
+ * hipGraph; blocking.                                                      */
+int mc_mlp_train(mc_ctx *ctx, const mc_mlp_args *args, const float *X, const float *Y, int32_t n, float *params,
+                 float *loss_log, void *ws, size_t ws_bytes, void *stream);
+
+/* Y = network(X) for n samples.  Stream-ordered.                           */
+int mc_mlp_predict(mc_ctx *ctx, const float *params, const float *X, int32_t n, float *Y, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

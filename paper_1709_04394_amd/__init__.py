@@ -68,6 +68,11 @@ class MucaStats(ctypes.Structure):
                 ("min_over_max", ctypes.c_double)]
 
 
+class MlpArgs(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
 class SweepArgs(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int32), ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("replica0", ctypes.c_uint32), ("sweep0", ctypes.c_uint64), ("nsweeps", ctypes.c_int32)]
@@ -101,6 +106,13 @@ _lib_fns = dict(
                                                          _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     mc_tune_sweep=_sig("mc_tune_sweep", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _c.c_double, _c.c_int32,
                                                    _vp]),
+    mc_mlp_param_count=_sig("mc_mlp_param_count", _c.c_int32, []),
+    mc_mlp_workspace_bytes=_sig("mc_mlp_workspace_bytes", _c.c_size_t, [_c.c_int32]),
+    mc_mlp_init=_sig("mc_mlp_init", _c.c_int, [_vp, _vp, _c.c_uint64, _vp]),
+    mc_mlp_grad=_sig("mc_mlp_grad", _c.c_int, [_vp, _vp, _vp, _vp, _c.c_int32, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    mc_mlp_train=_sig("mc_mlp_train", _c.c_int, [_vp, _c.POINTER(MlpArgs), _vp, _vp, _c.c_int32, _vp, _vp, _vp,
+                                                 _c.c_size_t, _vp]),
+    mc_mlp_predict=_sig("mc_mlp_predict", _c.c_int, [_vp, _vp, _vp, _c.c_int32, _vp, _vp]),
     mc_muca_workspace_bytes=_sig("mc_muca_workspace_bytes", _c.c_size_t, [_c.c_int32, _c.c_int32]),
     mc_muca_start=_sig("mc_muca_start", _c.c_int, [_vp, _c.c_int32, _c.c_int32, _c.c_uint64, _vp, _vp, _vp]),
     mc_muca_sweeps=_sig("mc_muca_sweeps", _c.c_int, [_vp, _c.c_int32, _c.c_int32, _vp, _vp, _c.POINTER(_c.c_double),
@@ -268,6 +280,40 @@ class Context:
             out.append(hist[off:off + n].reshape(nsteps + 1, L * L + 1))
             off += n
         return dict(Ctot=Ctot[:, :nsteps], lnQ=lnQ[:, :nsteps], lnZ=lnZ, hist=out)
+
+    # ---------------------------------------------------------------------- MLP
+    def mlp_init(self, seed):
+        p = torch.empty(int(_lib.mc_mlp_param_count()), dtype=torch.float32, device=self.device)
+        self._check(_lib.mc_mlp_init(self._h, _ptr(p), seed, _stream(self.device)), "mc_mlp_init")
+        return p
+
+    def _mlp_ws(self, n):
+        return torch.empty(int(_lib.mc_mlp_workspace_bytes(n)), dtype=torch.uint8, device=self.device)
+
+    def mlp_grad(self, params, X, Y):
+        n = Y.numel()
+        g = torch.empty_like(params)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        ws = self._mlp_ws(n)
+        self._check(_lib.mc_mlp_grad(self._h, _ptr(params), _ptr(X), _ptr(Y), n, _ptr(g), _ptr(loss), _ptr(ws),
+                                     ws.numel(), _stream(self.device)), "mc_mlp_grad")
+        return g, loss
+
+    def mlp_train(self, params, X, Y, epochs, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        n = Y.numel()
+        log = torch.empty(max(1, epochs), dtype=torch.float32, device=self.device)
+        ws = self._mlp_ws(n)
+        a = MlpArgs(epochs, lr, beta1, beta2, eps)
+        self._check(_lib.mc_mlp_train(self._h, ctypes.byref(a), _ptr(X), _ptr(Y), n, _ptr(params), _ptr(log),
+                                      _ptr(ws), ws.numel(), _stream(self.device)), "mc_mlp_train")
+        return log[:epochs]
+
+    def mlp_predict(self, params, X):
+        n = X.shape[0]
+        Y = torch.empty(n, dtype=torch.float32, device=self.device)
+        self._check(_lib.mc_mlp_predict(self._h, _ptr(params), _ptr(X), n, _ptr(Y), _stream(self.device)),
+                    "mc_mlp_predict")
+        return Y
 
     # ----------------------------------------------------------- multicanonical
     def muca_workspace(self, L, walkers):
