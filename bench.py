@@ -4,9 +4,10 @@
 Workload (the paper's benchmark size, Sec. "Checkerboard scheme": L = 4096):
 three 4096 x 4096 periodic 2D Ising lattices, int8 spins, hot start from seed
 7, checkerboard Metropolis at beta in {0.40, beta_c, 0.50}, Philox4x32-10
-randomness, (E, M) recorded after every sweep.  One step = sixteen full sweeps of
+randomness, (E, M) recorded after every sweep.  One step = one library call of
+100 full sweeps of
 each of the three lattices, including the per-sweep measurement; the default
-625 steps are the 10^4 sweeps per temperature of that workload.
+100 steps are the 10^4 sweeps per temperature of that workload.
 
 Prints one JSON line: spin flips per ns (attempted single-site updates per ns,
 the inverse of the paper's t_flip), the roofline fraction of the dominant
@@ -29,17 +30,60 @@ L = 4096
 SEED = 7
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_FLIP = 2.0
-SWEEPS_PER_STEP = 16
+SWEEPS_PER_STEP = 100
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile2d_L4096x3_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1709_04394_amd", "csrc", "k_tile2d.hip")
 
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=625)
-    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--steps", type=int, default=100)
+    p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--tile-plan", default=None,
+                   help="H,K,threads: use this launch shape instead of the autotuner's")
+    p.add_argument("--copy-probe", action="store_true",
+                   help="only run plain 1 GiB device-to-device copies (calibrates HBM byte counters)")
     return p.parse_args()
+
+
+def measured_traffic(plan):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by what
+    the counter reads for a plain copy of known size), or None when that
+    summary was taken on another kernel source or launch shape."""
+    import hashlib
+
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if kv.get("kernel_source_sha256") != src or kv.get("tile_plan") != "%d,%d,%d" % tuple(plan):
+        return None
+    return 1024.0 * (float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"]) +
+                     float(kv["write_kib_per_launch"]) * float(kv["write_scale"]))
+
+
+def copy_probe():
+    """Five plain copies of 1 GiB between two device buffers: each reads and
+    writes exactly 2^30 bytes, the yardstick for the FETCH_SIZE / WRITE_SIZE
+    counters of the sweep kernel."""
+    import torch
+
+    n = 1 << 30
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n, "copies": 5}))
 
 
 def cpu_baseline(target_s):
@@ -74,6 +118,9 @@ def main():
         print("bench.py measures one GPU only: this build runs on a single MI355X; "
               "--gpus %d is not supported" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    if a.copy_probe:
+        copy_probe()
+        return
     import torch
 
     import paper_1709_04394_amd as mcs
@@ -87,9 +134,14 @@ def main():
     nws = ctx.sweep_workspace_bytes(g)
     ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
     # launch shape from the autotuner (results never depend on it)
-    sa, sb = mcs.lattice_tensor(g, dev), mcs.lattice_tensor(g, dev)
-    plan = ctx.tune_sweep(g, sa, sb, BETA_C, sweeps=16)
-    del sa, sb
+    if a.tile_plan:
+        H, K, T = (int(x) for x in a.tile_plan.split(","))
+        ctx.set_tile_plan(g, H, K, T)
+        plan = ctx.get_tile_plan(g)
+    else:
+        sa, sb = mcs.lattice_tensor(g, dev), mcs.lattice_tensor(g, dev)
+        plan = ctx.tune_sweep(g, sa, sb, BETA_C, sweeps=16)
+        del sa, sb
     SPS = SWEEPS_PER_STEP
     EM = torch.empty((a.steps, SPS, 3, 2), dtype=torch.int64, device=dev)
     EMw = torch.empty((SPS, 3, 2), dtype=torch.int64, device=dev)
@@ -110,24 +162,41 @@ def main():
     flips = 3.0 * L * L * SPS * a.steps
     value = flips / (ms * 1e6)
 
-    # dominant kernel: the fused sweep launch (K sweeps of the three lattices,
-    # no measurement), timed with events around pairs of launches on the
-    # stream they run on
+    # dominant kernel: the packed -> packed fused launch (K sweeps of the three
+    # lattices with per-sweep E, M) that fills all but the first and last
+    # launch of a call.  Its average duration is the slope between calls of
+    # 2K and 22K sweeps (2 and 22 launches; both have the one int8 load and the
+    # one int8 store), timed with events on the stream the launches run on, so
+    # it includes the dispatch gap between back-to-back launches.
     H, K, T = plan
-    npair = 100
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(npair)]
-    torch.cuda.synchronize()
-    for i in range(npair):
-        evs[i][0].record()
-        ctx.sweep_betas(g, lat, BETAS, SEED, 2 * K, sweep0=10 ** 7 + 2 * K * i, replica0=0, ws=ws)
-        evs[i][1].record()
-    torch.cuda.synchronize()
-    launch_ms = sum(x.elapsed_time(y) for x, y in evs) / (2 * npair)
+    EMk = torch.empty((22 * K, 3, 2), dtype=torch.int64, device=dev)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def call_ms(n, sweep0):
+        x, y = ev(), ev()
+        x.record()
+        ctx.sweep_betas(g, lat, BETAS, SEED, n, sweep0=sweep0, replica0=0, EM=EMk[:n], ws=ws)
+        y.record()
+        torch.cuda.synchronize()
+        return x.elapsed_time(y)
+
+    slopes = []
+    sweep0 = (a.warmup + a.steps) * SPS
+    for _ in range(7):
+        t_short = call_ms(2 * K, sweep0)
+        sweep0 += 2 * K
+        t_long = call_ms(22 * K, sweep0)
+        sweep0 += 22 * K
+        slopes.append((t_long - t_short) / 20.0)
+    launch_ms = sorted(slopes)[len(slopes) // 2]
     achieved = BYTES_PER_FLIP * 3 * L * L * K / (launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic(plan)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "k_tile2d<%d,false>: %d sweeps of three 4096^2 int8 lattices per launch" % (K, K),
-            "avg_launch_us": launch_ms * 1e3, "tile_plan": {"H": H, "K": K, "threads": T}}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_tile2d<%d,true>, packed rows in and out: %d sweeps of three 4096^2 lattices with "
+                      "per-sweep E, M per launch" % (K, K),
+            "avg_launch_us": launch_ms * 1e3, "tile_plan": {"H": H, "K": K, "threads": T},
+            "algorithmic_bytes_per_launch": BYTES_PER_FLIP * 3 * L * L * K}
 
     out = {"metric": "spin flips/ns, % roofline (2D Ising L=4096)", "value": value, "unit": "spin flips/ns",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms / a.steps,

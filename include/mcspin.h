@@ -102,10 +102,13 @@ int mc_init(mc_ctx *ctx, const mc_geom *geom, void *spins, int32_t start, uint64
  * J: device int8 [dims][N] (geom->count is ignored).  Stream-ordered.       */
 int mc_couplings(mc_ctx *ctx, const mc_geom *geom, int8_t *J, uint64_t seed, void *stream);
 
-/* Bytes of scratch mc_sweep can use to run each sweep as one fused launch
- * (read one buffer, write the other).  With a smaller or NULL workspace
- * mc_sweep runs the two half-sweeps as two in-place launches; the results
- * are identical either way.                                                 */
+/* Bytes of scratch mc_sweep can use to run several sweeps per fused launch:
+ * two bit-packed copies of the lattices (count * Ly * Lx / 8 bytes each),
+ * between which the launches of one call ping-pong; only the first launch
+ * reads and only the last writes the caller's int8 lattices.  Non-zero for
+ * 2D int8 geometries with Lx a multiple of 64 (at most 16384).  With a
+ * smaller or NULL workspace mc_sweep runs the two half-sweeps as two in-place
+ * launches; the results are identical either way.                          */
 size_t mc_sweep_workspace_bytes(const mc_geom *geom);
 
 /* nsweeps checkerboard sweeps (Sec. "Checkerboard scheme"): one sweep updates
@@ -150,9 +153,11 @@ int mc_set_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t H, int32_t K, int
 int mc_get_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t *H, int32_t *K, int32_t *threads);
 
 /* Autotuner: times every admissible (H, K, threads) for this geometry with
- * `sweeps` sweeps at inverse temperature beta on two caller-provided scratch
- * lattices (device, count * N bytes each; overwritten) and keeps the fastest
- * shape on the context.  Synchronises the stream.                          */
+ * `sweeps` measured sweeps (per-sweep E, M, as mc_sweep with EM) at inverse
+ * temperature beta, in the steady state of a long call (packed rows in and
+ * out), on two caller-provided scratch lattices (device, count * N bytes
+ * each; overwritten), and keeps the fastest shape on the context.
+ * Synchronises the stream.                                                 */
 int mc_tune_sweep(mc_ctx *ctx, const mc_geom *geom, void *scratch_a, void *scratch_b, double beta,
                   int32_t sweeps, void *stream);
 

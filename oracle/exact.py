@@ -282,15 +282,27 @@ def _interpolate_mod(L, vals, p):
     return coef
 
 
+def _residue(Lp):
+    L, p = Lp
+    return _interpolate_mod(L, _poly_values_mod(L, p), p)
+
+
 @functools.lru_cache(maxsize=None)
-def exact_g(L):
+def exact_g(L, workers=1):
     """Exact integer g(E) of the L x L periodic ferromagnet, L even >= 4, as a
-    list indexed by level k = (E + 2N)/4 = 0..N (Python ints)."""
+    list indexed by level k = (E + 2N)/4 = 0..N (Python ints).  The primes are
+    independent: workers > 1 spreads them over that many processes."""
     assert L % 2 == 0 and L >= 4
     N = L * L
     nprimes = (N + 2) // 30 + 2
     primes = _primes_1_mod(2 * L, nprimes)
-    residues = [_interpolate_mod(L, _poly_values_mod(L, p), p) for p in primes]
+    if workers > 1:
+        import multiprocessing as mp
+
+        with mp.get_context("fork").Pool(workers) as pool:
+            residues = pool.map(_residue, [(L, p) for p in primes], chunksize=1)
+    else:
+        residues = [_residue((L, p)) for p in primes]
     # Garner's mixed-radix reconstruction, vectorised over the coefficients
     digits = []
     for i, p in enumerate(primes):

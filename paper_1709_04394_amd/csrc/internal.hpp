@@ -49,8 +49,12 @@ SweepTables build_tables(double beta);
 // fused 2D kernel (k_tile2d.hip)
 bool tile2d_supported(const SweepCall &c, int layout);
 size_t tile2d_lds_bytes(int Lx, int H, int K);
-hipError_t launch_tile2d(const SweepCall &c, const int8_t *src, int8_t *dst, uint64_t sweep0, int k, int H,
-                         int threads, int64_t *EM, int64_t em_stride, int64_t em_sweep0, hipStream_t s);
+// One fused launch of k sweeps (k = 0: conversion only).  src / dst are int8
+// lattices or, with in_packed / out_packed, the packed rows of the LDS layout
+// (per lattice Ly rows of 2 Lx/64 words, even-x array first); src != dst.
+hipError_t launch_tile2d(const SweepCall &c, const void *src, int in_packed, void *dst, int out_packed,
+                         uint64_t sweep0, int k, int H, int threads, int64_t *EM, int64_t em_stride, int64_t em_sweep0,
+                         hipStream_t s);
 TilePlan default_tile_plan(const Geom &g);
 
 // Sweep driver: chooses the fused kernel when the geometry and the workspace

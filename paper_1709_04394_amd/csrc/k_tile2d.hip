@@ -15,29 +15,38 @@
 //    four words (up, down, other parity, other parity shifted by one site) and
 //    the Metropolis classes (dE = 8, 4, <= 0) are a few 3-input bit operations
 //    (v_bitop3_b32).
+//  * Between the launches of one call the lattice stays in exactly that packed
+//    form in global scratch (one bit per spin, rows of 2 Lx/64 words), so only
+//    the first launch reads int8 and only the last writes int8: the traffic of
+//    the intermediate launches is an eighth of the int8 lattice's.
 //  * The random top bytes of those 32 sites are eight bit-planes taken straight
 //    from two Philox blocks; r32 < T becomes a bit-serial comparison of the
-//    planes with the threshold's top byte.  Ties (probability 1/256 per site)
-//    go to a workgroup queue in LDS and are settled together at the end of the
-//    half-sweep, one low-24-bit draw per tie, so a tie in one lane does not
-//    stall the other 63.
-//  * The energy of each sweep is summed over odd sites while they are updated
-//    (every bond has exactly one odd end), the magnetisation from popcounts of
-//    the band after the sweep; one int64 atomic per band and sweep.
+//    planes with the threshold's top byte.  Words with ties (a site whose top
+//    byte equals the threshold's, probability 1/256 per site) go to a
+//    workgroup queue in LDS, one item per word, and are settled together at
+//    the end of the half-sweep with one low-24-bit draw per tied site, so a tie
+//    in one lane does not stall the other 63.
+//  * Energy and magnetisation of each sweep come from the odd half-sweep:
+//    every bond has exactly one odd end, and when the odd sites of a row are
+//    updated its even sites are already final, so the band's own rows give E
+//    from the odd sites' four bonds and M from both parity words, with no
+//    extra pass; one int64 atomic per band and sweep.
 //  * Several lattices (each with its own inverse temperature) can share one
 //    launch, which gives taller bands and so less redone halo.
 #include "internal.hpp"
 
 namespace mcs {
 
-// Tie-queue items per workgroup (split evenly over its waves).  A wave expects
-// about 0.6 * 32 / 256 ~ 0.075 ties per 32-site task; a full segment falls
-// back to drawing the tie in place.
+// Tie-queue items per workgroup (split evenly over its waves).  One item is a
+// word with at least one tied site; a wave expects about
+// 1 - (1 - 0.6/256)^32 ~ 7% of its 32-site words to have one.  A full segment
+// falls back to drawing the ties in place.
 constexpr int kTieQueue = 512;
 
 struct Tile2DArgs {
-    const int8_t *src;
-    int8_t *dst;
+    const void *src;                // int8 lattices, or packed rows if in_packed
+    void *dst;                      // int8 lattices, or packed rows if out_packed
+    int in_packed, out_packed;
     int Lx, Ly, H;
     int64_t N;
     uint32_t seed_lo, seed_hi, replica0;
@@ -50,12 +59,28 @@ struct Tile2DArgs {
     int64_t em_sweep0;              // index of this launch's first sweep within EM
 };
 
+// Draw the low 24 bits of every tied site of one word (bits of p8 | p4) and
+// return the mask of those that are accepted.
+__device__ __forceinline__ uint32_t settle_ties(uint32_t p8, uint32_t p4, uint32_t blk, uint32_t rep,
+                                                uint32_t sweep_lo, uint32_t w3lo, uint32_t k0, uint32_t k1,
+                                                const Thr &t4, const Thr &t8)
+{
+    uint32_t pend = p8 | p4, acc = 0u;
+    while (pend) {
+        const int b = __builtin_ctz(pend);
+        pend &= pend - 1u;
+        const uint4 lo = philox(make_uint4(16u * blk + (uint32_t)b, rep, sweep_lo, w3lo), k0, k1);
+        if ((lo.x & 0xFFFFFFu) < (((p8 >> b) & 1u) ? t8.low : t4.low)) acc |= 1u << b;
+    }
+    return acc;
+}
+
 template <int K, bool MEASURE>
 __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
 {
     extern __shared__ uint32_t lds[];
-    __shared__ long long red[2][16];
-    __shared__ uint32_t q_j[kTieQueue], q_meta[kTieQueue];
+    __shared__ int red[2][16];
+    __shared__ uint32_t q_ws[kTieQueue], q_blk[kTieQueue], q_p8[kTieQueue], q_p4[kTieQueue];
     __shared__ uint32_t q_cnt[16];  // items queued by each wave in this half-sweep
     const int l = blockIdx.y;
     const int y0 = blockIdx.x * a.H;
@@ -65,8 +90,6 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
     const int Wd = a.Lx >> 6;
     const int nt = blockDim.x;
     const int tid = threadIdx.x;
-    const int8_t *src = a.src + (int64_t)l * a.N;
-    int8_t *dst = a.dst + (int64_t)l * a.N;
     const uint32_t rep = a.replica0 + (uint32_t)l;
     const Thr t4 = a.t4[a.per_lattice ? l : 0];
     const Thr t8 = a.t8[a.per_lattice ? l : 0];
@@ -98,37 +121,47 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
     const uint32_t wq_cap = (uint32_t)(kTieQueue / nwaves), wq_base = (uint32_t)wave * wq_cap;
     uint32_t wq_n = 0;
 
-    // ---- load rows y0-R .. y0+Hh+R-1 and pack: sign bit of each byte,
-    // even-x sites to array 0, odd-x sites to array 1.
-    for (int r = r0; r < rows; r += Q) {
-        const int8_t *row = src + (int64_t)lat_row(r) * a.Lx;
-        for (int w = w0; w < Wd; w += P) {
-            const uint4 *p = (const uint4 *)(row + 64 * w);
-            uint32_t ev = 0, od = 0;
+    // ---- load rows y0-R .. y0+Hh+R-1
+    if (a.in_packed) {
+        // packed row y of lattice l: 2 Wd words at (l Ly + y) 2 Wd, even array first
+        const uint2 *src = (const uint2 *)a.src + (int64_t)l * a.Ly * Wd;
+        for (int r = r0; r < rows; r += Q) {
+            const uint2 *row = src + (int64_t)lat_row(r) * Wd;
+            for (int w = w0; w < Wd; w += P) ((uint2 *)lds)[r * Wd + w] = row[w];
+        }
+    } else {
+        // int8: sign bit of each byte, even-x sites to array 0, odd-x to array 1
+        const int8_t *src = (const int8_t *)a.src + (int64_t)l * a.N;
+        for (int r = r0; r < rows; r += Q) {
+            const int8_t *row = src + (int64_t)lat_row(r) * a.Lx;
+            for (int w = w0; w < Wd; w += P) {
+                const uint4 *p = (const uint4 *)(row + 64 * w);
+                uint32_t ev = 0, od = 0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint4 v = p[q];
-                const uint32_t dw[4] = {v.x, v.y, v.z, v.w};
+                for (int q = 0; q < 4; ++q) {
+                    const uint4 v = p[q];
+                    const uint32_t dw[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    // sign bits at 7, 15, 23, 31 -> m + (m << 15) puts the two
-                    // even-x bits at 22..23 and the two odd-x bits at 30..31
-                    const uint32_t m = dw[i] & 0x80808080u;
-                    const uint32_t Pm = m + (m << 15);
-                    const int sh = 2 * (4 * q + i);
-                    ev |= ((Pm >> 22) & 3u) << sh;
-                    od |= (Pm >> 30) << sh;
+                    for (int i = 0; i < 4; ++i) {
+                        // sign bits at 7, 15, 23, 31 -> m + (m << 15) puts the two
+                        // even-x bits at 22..23 and the two odd-x bits at 30..31
+                        const uint32_t m = dw[i] & 0x80808080u;
+                        const uint32_t Pm = m + (m << 15);
+                        const int sh = 2 * (4 * q + i);
+                        ev |= ((Pm >> 22) & 3u) << sh;
+                        od |= (Pm >> 30) << sh;
+                    }
                 }
+                lds[widx(r, 0, w)] = ev;
+                lds[widx(r, 1, w)] = od;
             }
-            lds[widx(r, 0, w)] = ev;
-            lds[widx(r, 1, w)] = od;
         }
     }
     __syncthreads();
 
     for (int s = 0; s < K; ++s) {
         const uint64_t sweep = a.sweep0 + (uint64_t)s;
-        long long e_acc = 0;
+        int e_acc = 0, m_acc = 0;  // this thread's share of the band's E and M
         for (int c = 0; c < 2; ++c) {
             const int p = 2 * s + c;
             const int r_lo = p + 1, r_hi = rows - p - 1;
@@ -168,37 +201,35 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
                     compare_planes(X, m8, lt8, eq8);
                     compare_planes(X, m4, lt4, eq4);
                     uint32_t acc = MCS_BOP3(ge2, c8, lt8, MCS_A | (MCS_B & MCS_C)) | (c4 & lt4);
-                    uint32_t pend = (c8 & eq8) | (c4 & eq4);
-                    // append ties to this wave's queue segment: one item per
-                    // pending lane per round, offsets from ballot + mbcnt
-                    uint64_t m = __ballot(pend != 0u);
-                    while (m) {
-                        const uint32_t off = __builtin_amdgcn_mbcnt_hi(
-                            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                        if (pend) {
-                            const int b = __builtin_ctz(pend);
-                            pend &= pend - 1u;
-                            const uint32_t cls8 = (c8 >> b) & 1u;
-                            const uint32_t pos = wq_n + off;
+                    const uint32_t p8 = c8 & eq8, p4 = c4 & eq4;
+                    // words with ties join this wave's queue segment, one item
+                    // per word, offsets from ballot + mbcnt
+                    const uint64_t m = __ballot((p8 | p4) != 0u);
+                    if (m) {
+                        if (p8 | p4) {
+                            const uint32_t pos = wq_n + __builtin_amdgcn_mbcnt_hi(
+                                                            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                             if (pos < wq_cap) {
-                                q_j[wq_base + pos] = 16u * blk + (uint32_t)b;
-                                q_meta[wq_base + pos] =
-                                    (uint32_t)ws | ((uint32_t)b << 16) | (cls8 << 21) | ((uint32_t)interior << 22);
+                                q_ws[wq_base + pos] = (uint32_t)ws | ((uint32_t)interior << 31);
+                                q_blk[wq_base + pos] = blk;
+                                q_p8[wq_base + pos] = p8;
+                                q_p4[wq_base + pos] = p4;
                             } else {
-                                const uint4 lo = philox(
-                                    make_uint4(16u * blk + (uint32_t)b, rep, (uint32_t)sweep, w3lo), a.seed_lo,
-                                    a.seed_hi);
-                                if ((lo.x & 0xFFFFFFu) < (cls8 ? t8.low : t4.low)) acc |= 1u << b;
+                                acc |= settle_ties(p8, p4, blk, rep, (uint32_t)sweep, w3lo, a.seed_lo, a.seed_hi, t4,
+                                                   t8);
                             }
                         }
                         wq_n = min(wq_cap, wq_n + (uint32_t)__popcll(m));
-                        m = __ballot(pend != 0u);
                     }
-                    lds[ws] = S ^ acc;
-                    if (interior)
-                        e_acc += 2 * (long long)(__builtin_popcount(u1 ^ acc) + __builtin_popcount(u2 ^ acc) +
-                                                 __builtin_popcount(u3 ^ acc) + __builtin_popcount(u4 ^ acc)) -
+                    const uint32_t Sn = S ^ acc;
+                    lds[ws] = Sn;
+                    if (interior) {
+                        // bonds of the odd sites after their update: 2 (#anti-aligned) - 4 each
+                        e_acc += 2 * (int)(__builtin_popcount(u1 ^ acc) + __builtin_popcount(u2 ^ acc) +
+                                           __builtin_popcount(u3 ^ acc) + __builtin_popcount(u4 ^ acc)) -
                                  128;
+                        m_acc += 64 - 2 * (int)(__builtin_popcount(Sn) + __builtin_popcount(O));
+                    }
                 }
             }
             // lanes that left the row loop early hold an older (smaller) fill
@@ -207,52 +238,59 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
             for (int off = 32; off > 0; off >>= 1) wq_n = max(wq_n, (uint32_t)__shfl_xor((int)wq_n, off, 64));
             if ((tid & 63) == 0) q_cnt[wave] = wq_n;
             __syncthreads();
-            // settle the queued ties: low 24 bits of r32 against the threshold;
-            // item i of the concatenated segments goes to thread i (mod nt)
+            // settle the queued words: item i of the concatenated segments goes
+            // to thread i (mod nt); every item is a different word
             uint32_t total = 0;
             for (int sg = 0; sg < nwaves; ++sg) total += q_cnt[sg];
             for (uint32_t i = tid; i < total; i += nt) {
                 uint32_t sg = 0, k = i;
                 while (k >= q_cnt[sg]) k -= q_cnt[sg++];
                 const uint32_t item = sg * wq_cap + k;
-                const uint32_t meta = q_meta[item];
-                const uint4 lo = philox(make_uint4(q_j[item], rep, (uint32_t)sweep, w3lo), a.seed_lo, a.seed_hi);
-                const bool cls8 = (meta >> 21) & 1u;
-                if ((lo.x & 0xFFFFFFu) < (cls8 ? t8.low : t4.low)) {
-                    atomicXor(&lds[meta & 0xFFFFu], 1u << ((meta >> 16) & 31u));
-                    if (MEASURE && ((meta >> 22) & 1u)) e_acc += cls8 ? 8 : 4;
+                const uint32_t p8 = q_p8[item], p4 = q_p4[item], wsm = q_ws[item];
+                const uint32_t acc =
+                    settle_ties(p8, p4, q_blk[item], rep, (uint32_t)sweep, w3lo, a.seed_lo, a.seed_hi, t4, t8);
+                if (acc) {
+                    const uint32_t ws = wsm & 0x7FFFFFFFu, old = lds[ws];
+                    lds[ws] = old ^ acc;
+                    if (MEASURE && (wsm >> 31)) {
+                        e_acc += 8 * __builtin_popcount(acc & p8) + 4 * __builtin_popcount(acc & p4);
+                        m_acc += 2 * (2 * __builtin_popcount(old & acc) - __builtin_popcount(acc));
+                    }
+                }
+            }
+            if (MEASURE && c == 1) {
+                e_acc = wave_sum_i(e_acc);
+                m_acc = wave_sum_i(m_acc);
+                if ((tid & 63) == 0) {
+                    red[0][wave] = e_acc;
+                    red[1][wave] = m_acc;
                 }
             }
             __syncthreads();
             wq_n = 0;
         }
-        if (MEASURE) {
-            long long m_acc = 0;
-            for (int r = R + r0; r < R + Hh; r += Q)
-                for (int w = w0; w < Wd; w += P)
-                    m_acc += 64 - 2 * (__builtin_popcount(lds[widx(r, 0, w)]) + __builtin_popcount(lds[widx(r, 1, w)]));
-            e_acc = wave_sum(e_acc);
-            m_acc = wave_sum(m_acc);
-            if ((tid & 63) == 0) {
-                red[0][tid >> 6] = e_acc;
-                red[1][tid >> 6] = m_acc;
+        if (MEASURE && tid == 0) {
+            long long te = 0, tm = 0;
+            for (int i = 0; i < nwaves; ++i) {
+                te += red[0][i];
+                tm += red[1][i];
             }
-            __syncthreads();
-            if (tid == 0) {
-                long long te = 0, tm = 0;
-                for (int i = 0; i < (nt >> 6); ++i) {
-                    te += red[0][i];
-                    tm += red[1][i];
-                }
-                int64_t *em = a.EM + (a.em_sweep0 + s) * a.em_stride + 2 * l;
-                atomicAdd((unsigned long long *)&em[0], (unsigned long long)te);
-                atomicAdd((unsigned long long *)&em[1], (unsigned long long)tm);
-            }
-            __syncthreads();
+            int64_t *em = a.EM + (a.em_sweep0 + s) * a.em_stride + 2 * l;
+            atomicAdd((unsigned long long *)&em[0], (unsigned long long)te);
+            atomicAdd((unsigned long long *)&em[1], (unsigned long long)tm);
         }
     }
 
-    // ---- unpack the band's own rows and store them
+    // ---- store the band's own rows
+    if (a.out_packed) {
+        uint2 *dst = (uint2 *)a.dst + (int64_t)l * a.Ly * Wd;
+        for (int r = R + r0; r < R + Hh; r += Q) {
+            uint2 *row = dst + (int64_t)(y0 + r - R) * Wd;
+            for (int w = w0; w < Wd; w += P) row[w] = ((const uint2 *)lds)[r * Wd + w];
+        }
+        return;
+    }
+    int8_t *dst = (int8_t *)a.dst + (int64_t)l * a.N;
     for (int r = R + r0; r < R + Hh; r += Q) {
         int8_t *row = dst + (int64_t)(y0 + r - R) * a.Lx;
         for (int w = w0; w < Wd; w += P) {
@@ -291,17 +329,29 @@ static hipError_t launch_k(const Tile2DArgs &a, int count, int threads, hipStrea
     const int tiles = (a.Ly + a.H - 1) / a.H;
     const size_t lds = tile2d_lds_bytes(a.Lx, a.H, K);
     dim3 grid((unsigned)tiles, (unsigned)count);
+    // allow the largest dynamic LDS a plan may ask for (64 KB) next to the
+    // static tie queue
+    static bool attr[2] = {false, false};
+    if (!attr[a.EM ? 1 : 0]) {
+        const void *f = a.EM ? (const void *)k_tile2d<K, true> : (const void *)k_tile2d<K, false>;
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+        if (e != hipSuccess) return e;
+        attr[a.EM ? 1 : 0] = true;
+    }
     if (a.EM) hipLaunchKernelGGL((k_tile2d<K, true>), grid, dim3(threads), lds, s, a);
     else hipLaunchKernelGGL((k_tile2d<K, false>), grid, dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_tile2d(const SweepCall &c, const int8_t *src, int8_t *dst, uint64_t sweep0, int k, int H,
-                         int threads, int64_t *EM, int64_t em_stride, int64_t em_sweep0, hipStream_t s)
+hipError_t launch_tile2d(const SweepCall &c, const void *src, int in_packed, void *dst, int out_packed,
+                         uint64_t sweep0, int k, int H, int threads, int64_t *EM, int64_t em_stride, int64_t em_sweep0,
+                         hipStream_t s)
 {
     Tile2DArgs a;
     a.src = src;
     a.dst = dst;
+    a.in_packed = in_packed;
+    a.out_packed = out_packed;
     a.Lx = c.g.Lx;
     a.Ly = c.g.Ly;
     a.H = H;
@@ -316,10 +366,11 @@ hipError_t launch_tile2d(const SweepCall &c, const int8_t *src, int8_t *dst, uin
         a.t4[i] = t.met[1];
         a.t8[i] = t.met[2];
     }
-    a.EM = EM;
+    a.EM = k > 0 ? EM : nullptr;
     a.em_stride = em_stride;
     a.em_sweep0 = em_sweep0;
     switch (k) {
+    case 0: return launch_k<0>(a, c.g.count, threads, s);
     case 1: return launch_k<1>(a, c.g.count, threads, s);
     case 2: return launch_k<2>(a, c.g.count, threads, s);
     case 3: return launch_k<3>(a, c.g.count, threads, s);

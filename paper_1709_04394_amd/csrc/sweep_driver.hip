@@ -7,10 +7,13 @@
 
 namespace mcs {
 
+// Bytes of one packed copy of all lattices: one bit per spin.
+static size_t packed_bytes(const Geom &g) { return (size_t)g.count * (size_t)g.Ly * (size_t)(g.Lx / 8); }
+
+// Two packed copies (ping-pong between the launches of one call).
 size_t fused_workspace_bytes(const Geom &g, int layout)
 {
-    if (layout == MC_INT8 && g.dims == 2 && g.Lx % 64 == 0 && g.Lx <= 16384)
-        return (size_t)g.count * (size_t)g.N;
+    if (layout == MC_INT8 && g.dims == 2 && g.Lx % 64 == 0 && g.Lx <= 16384) return 2 * packed_bytes(g);
     return 0;
 }
 
@@ -30,13 +33,19 @@ TilePlan default_tile_plan(const Geom &g)
     while (p.H > 4 && tile2d_lds_bytes(g.Lx, p.H, p.K) > 65536) p.H /= 2;
     const int tasks = (p.H + 2 * p.K) * (g.Lx / 64);
     p.threads = std::min(1024, std::max(64, ((tasks + 63) / 64) * 64));
+    while (g.Lx / 64 > p.threads && (g.Lx / 64) % p.threads) p.threads += 64;
     return p;
 }
 
+// A row of Wd = Lx/64 words is spread over the threads; when it is wider than
+// the workgroup every thread must take the same number of words, because the
+// tie queue's fill level is kept wave-uniform by all lanes taking part in the
+// same ballots.
 static bool plan_ok(const Geom &g, const TilePlan &p)
 {
+    const int Wd = g.Lx / 64;
     return p.H >= 1 && p.K >= 1 && p.K <= 8 && p.threads >= 64 && p.threads <= 1024 && p.threads % 64 == 0 &&
-           tile2d_lds_bytes(g.Lx, std::min(p.H, g.Ly), p.K) <= 65536;
+           (Wd <= p.threads || Wd % p.threads == 0) && tile2d_lds_bytes(g.Lx, std::min(p.H, g.Ly), p.K) <= 65536;
 }
 
 static TilePlan plan_for(mc_ctx *ctx, const Geom &g)
@@ -46,33 +55,39 @@ static TilePlan plan_for(mc_ctx *ctx, const Geom &g)
     return default_tile_plan(g);
 }
 
-// Split n sweeps into launches of at most K sweeps, preferring an even number
-// of launches so the result lands back in the caller's buffer.
+// Split n >= 1 sweeps into launches of at most K sweeps, sizes as equal as
+// possible; at least two launches (a launch never writes its own input), the
+// second of zero sweeps when n = 1.
 static std::vector<int> split_launches(int n, int K)
 {
-    int m = (n + K - 1) / K;
-    if ((m & 1) && m < n) ++m;
+    if (n == 1) return {1, 0};
+    const int m = std::max(2, (n + K - 1) / K);
     std::vector<int> sizes(m, n / m);
     for (int i = 0; i < n % m; ++i) sizes[i] += 1;
     return sizes;
 }
 
-static int run_fused(mc_ctx *ctx, const SweepCall &c, const TilePlan &p, int8_t *spins, int8_t *ws,
-                     uint64_t sweep0, int nsweeps, int64_t *EM, int64_t em_stride, hipStream_t s)
+// Launch i reads the caller's int8 lattices (i = 0) or packed copy (i - 1) & 1
+// of the workspace, and writes packed copy i & 1 or, for the last launch, the
+// caller's lattices.
+static int run_fused(mc_ctx *ctx, const SweepCall &c, const TilePlan &p, int8_t *spins, char *ws, uint64_t sweep0,
+                     int nsweeps, int64_t *EM, int64_t em_stride, hipStream_t s)
 {
     hipError_t e = hipSuccess;
     if (EM) e = launch_fill_i64(EM, (int64_t)nsweeps * em_stride, 0, s);
     const std::vector<int> sizes = split_launches(nsweeps, p.K);
+    char *pk[2] = {ws, ws + packed_bytes(c.g)};
     int done = 0;
     const int H = std::min(p.H, c.g.Ly);
-    for (size_t i = 0; i < sizes.size() && e == hipSuccess; ++i) {
-        const int8_t *src = (i & 1) ? ws : spins;
-        int8_t *dst = (i & 1) ? spins : ws;
-        e = launch_tile2d(c, src, dst, sweep0 + (uint64_t)done, sizes[i], H, p.threads, EM, em_stride, done, s);
+    const size_t m = sizes.size();
+    for (size_t i = 0; i < m && e == hipSuccess; ++i) {
+        const bool first = i == 0, last = i + 1 == m;
+        const void *src = first ? (const void *)spins : (const void *)pk[(i - 1) & 1];
+        void *dst = last ? (void *)spins : (void *)pk[i & 1];
+        e = launch_tile2d(c, src, first ? 0 : 1, dst, last ? 0 : 1, sweep0 + (uint64_t)done, sizes[i], H, p.threads,
+                          EM, em_stride, done, s);
         done += sizes[i];
     }
-    if (e == hipSuccess && (sizes.size() & 1))
-        e = hipMemcpyAsync(spins, ws, (size_t)c.g.count * (size_t)c.g.N, hipMemcpyDeviceToDevice, s);
     return device_check(ctx, e, "mc_sweep fused launch");
 }
 
@@ -82,7 +97,7 @@ int run_sweeps(mc_ctx *ctx, const SweepCall &c, int layout, void *spins, uint64_
     if (tile2d_supported(c, layout) && ws && ws_bytes >= fused_workspace_bytes(c.g, layout)) {
         const TilePlan p = plan_for(ctx, c.g);
         if (plan_ok(c.g, p))
-            return run_fused(ctx, c, p, (int8_t *)spins, (int8_t *)ws, sweep0, nsweeps, EM, em_stride, s);
+            return run_fused(ctx, c, p, (int8_t *)spins, (char *)ws, sweep0, nsweeps, EM, em_stride, s);
     }
     for (int t = 0; t < nsweeps; ++t) {
         const uint64_t sweep = sweep0 + (uint64_t)t;
@@ -156,7 +171,12 @@ int mc_tune_sweep(mc_ctx *ctx, const mc_geom *geom, void *scratch_a, void *scrat
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(ctx, MC_E_DEVICE, "hipEventCreate failed");
+    // a hot lattice, packed into scratch_b
     hipError_t e = launch_init_int8(g, (int8_t *)scratch_a, 1, 1, 0, s);
+    if (e == hipSuccess) e = launch_tile2d(c, scratch_a, 0, scratch_b, 1, 0, 0, std::min(16, g.Ly), 256, nullptr, 0, 0, s);
+    // per-sweep E, M of the timed launches: past the packed copy in scratch_a
+    // (count N / 8 bytes of packed rows; count N / 2 >= that + 16 K count)
+    int64_t *em = (int64_t *)((char *)scratch_a + (size_t)g.count * (size_t)g.N / 2);
     TilePlan best = default_tile_plan(g);
     float best_ms = 1e30f;
     const int Hs[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128};
@@ -173,20 +193,24 @@ int mc_tune_sweep(mc_ctx *ctx, const mc_geom *geom, void *scratch_a, void *scrat
                 if (!plan_ok(g, p) || e != hipSuccess) continue;
                 int n = std::max(sweeps, 2 * K);
                 n -= n % (2 * K);
-                // warm-up launch, then timed launches
-                e = launch_tile2d(c, (int8_t *)scratch_a, (int8_t *)scratch_b, 0, K, H, T, nullptr, 0, 0, s);
+                // the steady state of a long measured call: packed -> packed
+                // launches between the two scratch buffers, per-sweep E, M into
+                // the unused tail of scratch_a; a warm-up launch, then the best
+                // of two timed runs
+                e = launch_tile2d(c, scratch_b, 1, scratch_a, 1, 0, K, H, T, em, 2 * g.count, 0, s);
+                float ms = 1e30f;
+                for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+                    hipEventRecord(e0, s);
+                    for (int i = 0; i < n / K && e == hipSuccess; ++i)
+                        e = launch_tile2d(c, (i & 1) ? scratch_b : scratch_a, 1, (i & 1) ? scratch_a : scratch_b, 1,
+                                          (uint64_t)i * K, K, H, T, em, 2 * g.count, 0, s);
+                    hipEventRecord(e1, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    float t = 0;
+                    if (e == hipSuccess) hipEventElapsedTime(&t, e0, e1);
+                    ms = std::min(ms, t / (float)n);
+                }
                 if (e != hipSuccess) break;
-                hipEventRecord(e0, s);
-                for (int i = 0; i < n / K && e == hipSuccess; ++i)
-                    e = launch_tile2d(c, (i & 1) ? (int8_t *)scratch_b : (int8_t *)scratch_a,
-                                      (i & 1) ? (int8_t *)scratch_a : (int8_t *)scratch_b, (uint64_t)i * K, K, H, T,
-                                      nullptr, 0, 0, s);
-                hipEventRecord(e1, s);
-                if (e != hipSuccess) break;
-                if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
-                float ms = 0;
-                hipEventElapsedTime(&ms, e0, e1);
-                ms /= (float)n;
                 if (ms < best_ms) {
                     best_ms = ms;
                     best = p;

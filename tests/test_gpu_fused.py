@@ -2,8 +2,9 @@
 per launch with a redone halo) against the CPU oracle, and launch-shape
 invariance: every admissible (band height, sweeps per launch, threads) gives
 the same bits, including ragged last bands, bands taller than the lattice,
-an odd number of launches (result copied back), several lattices per launch
-and sweep numbers above 2^32.
+single sweeps (a sweep launch plus a conversion-only launch), calls whose
+intermediate launches run on the packed copy in the workspace, several
+lattices per launch, tie-queue overflow and sweep numbers above 2^32.
 """
 import numpy as np
 import pytest
@@ -22,12 +23,13 @@ def ctx():
     return mcs.Context(0)
 
 
-def _gpu_run(ctx, shape, beta, seed, nsweeps, sweep0, count, replica0, plan):
+def _gpu_run(ctx, shape, beta, seed, nsweeps, sweep0, count, replica0, plan, start=None):
+    start = mcs.HOT if start is None else start
     g = mcs.make_geom(2, shape, count=count)
     spins = mcs.lattice_tensor(g)
-    ctx.init(g, spins, mcs.HOT, seed, replica0)
+    ctx.init(g, spins, start, seed, replica0)
     ws = torch.empty(ctx.sweep_workspace_bytes(g), dtype=torch.uint8, device="cuda")
-    assert ws.numel() == count * g.N
+    assert ws.numel() == 2 * count * g.N // 8  # two bit-packed copies
     if plan is not None:
         ctx.set_tile_plan(g, *plan)
     EM = torch.empty((nsweeps, count, 2), dtype=torch.int64, device="cuda")
@@ -36,10 +38,11 @@ def _gpu_run(ctx, shape, beta, seed, nsweeps, sweep0, count, replica0, plan):
     return spins.cpu().numpy(), EM.cpu().numpy()
 
 
-def _oracle_run(shape, beta, seed, nsweeps, sweep0, count, replica0):
+def _oracle_run(shape, beta, seed, nsweeps, sweep0, count, replica0, start=None):
+    start = oracle.HOT if start is None else start
     out_s, out_em = [], []
     for l in range(count):
-        s = oracle.init(2, shape, oracle.HOT, seed, replica0 + l)
+        s = oracle.init(2, shape, start, seed, replica0 + l)
         em = oracle.sweep(2, shape, s, beta, seed, replica0 + l, sweep0, nsweeps)
         out_s.append(s)
         out_em.append(em)
@@ -50,7 +53,7 @@ def _oracle_run(shape, beta, seed, nsweeps, sweep0, count, replica0):
                                         ((64, 64), (5, 4, 512)), ((64, 64), (64, 8, 1024)),
                                         ((128, 36), (7, 2, 192)), ((192, 20), (64, 3, 256)),
                                         ((64, 4), (2, 1, 64)), ((64, 6), (4, 4, 128)), ((256, 132), None)])
-@pytest.mark.parametrize("nsweeps", [1, 3, 8])
+@pytest.mark.parametrize("nsweeps", [1, 3, 8, 21])
 def test_fused_matches_oracle(ctx, shape, plan, nsweeps):
     beta, seed, sweep0, count, rep0 = 0.4406868, 29, (1 << 32) - 2, 2, 3
     gs, gem = _gpu_run(ctx, shape, beta, seed, nsweeps, sweep0, count, rep0, plan)
@@ -60,11 +63,13 @@ def test_fused_matches_oracle(ctx, shape, plan, nsweeps):
 
 
 def test_fused_tie_queue_overflow(ctx):
-    # one wave per band of 56 rows of 8192 sites: ~600 threshold ties per
-    # half-sweep, more than the 512-item tie queue, so some are drawn in place
+    # one wave per band of 56 rows of 8192 sites from a cold start: every site
+    # is in the dE = 8 class, so about 1 - (255/256)^32 ~ 12% of the ~7900
+    # words of a half-sweep hold a tie, more than the 512-item queue; the rest
+    # are drawn in place
     shape = (8192, 112)
-    gs, gem = _gpu_run(ctx, shape, 0.44, 5, 4, 0, 1, 0, (56, 2, 64))
-    os_, oem = _oracle_run(shape, 0.44, 5, 4, 0, 1, 0)
+    gs, gem = _gpu_run(ctx, shape, 0.44, 5, 4, 0, 1, 0, (56, 2, 64), start=mcs.COLD)
+    os_, oem = _oracle_run(shape, 0.44, 5, 4, 0, 1, 0, start=oracle.COLD)
     assert np.array_equal(gs, os_) and np.array_equal(gem, oem)
 
 
