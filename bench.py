@@ -44,6 +44,11 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--tile-plan", default=None,
                    help="H,K,threads: use this launch shape instead of the autotuner's")
+    p.add_argument("--no-rows", action="store_true", help="skip the other hot-path rows' throughput lines")
+    p.add_argument("--muca", default=None,
+                   help="comma-separated test sizes (of 64,96,128): run the learned-vs-plain multicanonical "
+                        "comparison (minutes) and add it to the line")
+    p.add_argument("--muca-prod", type=int, default=20000, help="production sweeps per arm at the largest size")
     p.add_argument("--copy-probe", action="store_true",
                    help="only run plain 1 GiB device-to-device copies (calibrates HBM byte counters)")
     return p.parse_args()
@@ -68,6 +73,162 @@ def measured_traffic(plan):
         return None
     return 1024.0 * (float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"]) +
                      float(kv["write_kib_per_launch"]) * float(kv["write_scale"]))
+
+
+def _events_ms(torch, fn, reps):
+    """Median event-timed duration of fn() on the current stream."""
+    out = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        out.append(a.elapsed_time(b))
+    return sorted(out)[len(out) // 2]
+
+
+def row_measurements(torch, mcs, ctx, dev):
+    """Throughput of the other hot-path rows on their workloads' shapes, each
+    timed with events around library calls (inputs resident in HBM), with the
+    algorithmic bytes that an unfused sweep moves: int8 2 B per flip (+3 B of
+    couplings per site for the spin glass), MSC64 0.25 B per flip (1 bit in
+    and out).  Short runs: these are throughput figures, not physics."""
+    rows = {}
+    HB = mcs.HEATBATH
+
+    def sweep_row(name, geom, flips_per_sweep, bytes_per_flip, beta, rule, nsw, J=None, start=mcs.HOT, seed=11):
+        lat = mcs.lattice_tensor(geom, dev)
+        ctx.init(geom, lat, start, seed, 0)
+        EM = torch.empty((nsw, geom.count * (64 if geom.layout == mcs.MSC64 else 1), 2), dtype=torch.int64,
+                         device=dev)
+        nb = ctx.sweep_workspace_bytes(geom)
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev) if nb else None
+        ctx.sweep(geom, lat, beta, seed, 1, rule=rule, J=J, EM=EM[:1], ws=ws)
+        sweep0 = [1]
+
+        def run():
+            ctx.sweep(geom, lat, beta, seed, nsw, sweep0=sweep0[0], rule=rule, J=J, EM=EM, ws=ws)
+            sweep0[0] += nsw
+
+        ms = _events_ms(torch, run, 3)
+        fpn = flips_per_sweep * nsw / (ms * 1e6)
+        gbs = fpn * bytes_per_flip
+        rows[name] = {"value": fpn, "unit": "spin flips/ns", "ms_per_sweep": ms / nsw,
+                      "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": gbs / HBM_PEAK_GBS}}
+        del lat, EM, ws
+
+    g = mcs.make_geom(3, 256)
+    sweep_row("3d_int8_heatbath_256", g, 256 ** 3, 2.0, 0.2216546, HB, 20)
+    g = mcs.make_geom(2, L, layout=mcs.MSC64, count=1)
+    sweep_row("2d_msc64_4096", g, 64 * L * L, 0.25, BETA_C, mcs.METROPOLIS, 10, seed=7)
+    g = mcs.make_geom(3, 256, layout=mcs.MSC64, count=1)
+    sweep_row("3d_msc64_heatbath_256", g, 64 * 256 ** 3, 0.25, 0.2216546, HB, 5)
+    g = mcs.make_geom(3, 32)
+    J = torch.empty(3 * 32 ** 3, dtype=torch.int8, device=dev)
+    ctx.couplings(g, J, 13)
+    sweep_row("3d_ea_int8_32", g, 32 ** 3, 2.0 + 3.0, 1.0, mcs.METROPOLIS, 200, J=J, seed=13)
+
+    # population annealing: 4 populations x 16384 replicas, L in {16, 32, 64, 128},
+    # 200 steps of theta = 10 sweeps (the whole anneal, one captured graph)
+    import numpy as np
+
+    Ls, R = [16, 32, 64, 128], 16384
+    beta = np.arange(201) / 200.0
+    pops = ctx.pa_population_tensors(Ls, R)
+    nb = ctx.pa_workspace_bytes(Ls, R, 10, beta)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    import time as _t
+
+    ctx.pa_anneal(Ls, R, 10, 17, beta, pops, step_first=1, nsteps=2, ws=ws)
+    t0 = _t.perf_counter()
+    ctx.pa_anneal(Ls, R, 10, 17, beta, pops, step_first=1, nsteps=200, ws=ws)
+    el = _t.perf_counter() - t0
+    flips = 200 * 10 * R * sum(x * x for x in Ls)
+    rows["pa_4x16384_L16-128_200steps"] = {"value": flips / (el * 1e9), "unit": "spin flips/ns", "seconds": el,
+                                           "note": "whole blocking call: graph build, 200 steps, ln Z and histograms"}
+    del pops, ws
+
+    # multicanonical walkers: 4096 walkers of 128 x 128, sequential updates
+    Lm, Wm = 128, 4096
+    spins, E = ctx.muca_start(Lm, Wm, 147)
+    wsm = ctx.muca_workspace(Lm, Wm)
+    H = torch.zeros(Lm * Lm // 2 + 1, dtype=torch.int64, device=dev)
+    lnW = np.zeros(Lm * Lm // 2 + 1)
+    ctx.muca_sweeps(Lm, spins, E, lnW, 147, 0, 1, 1, H, wsm)
+    t0 = _t.perf_counter()
+    ctx.muca_sweeps(Lm, spins, E, lnW, 147, 1, 4, 1, H, wsm)
+    el = _t.perf_counter() - t0
+    rows["muca_4096_walkers_L128"] = {"value": Wm * Lm * Lm * 4 / (el * 1e9), "unit": "single-site updates/ns",
+                                      "ms_per_sweep": el * 250.0}
+    return rows
+
+
+def exact_lng(L):
+    """Exact ln g over the window levels from the stored files (written by
+    tests/golden/make_exact_lng.py from the oracle's exact density of states)."""
+    import numpy as np
+
+    return np.loadtxt(os.path.join(ROOT, "tests", "golden", "lng_L%d.txt" % L))
+
+
+def lng_error(lng_est, lng_ex):
+    """max |ln g_est - ln g_exact| over the window levels with states, after
+    matching the two normalisations (log-sum-exp over those levels)."""
+    import numpy as np
+
+    m = np.isfinite(lng_ex)
+    if not np.all(np.isfinite(lng_est[m])):
+        return float("inf")
+    a, b = lng_est[m], lng_ex[m]
+    c = np.logaddexp.reduce(b) - np.logaddexp.reduce(a)
+    return float(np.max(np.abs(a + c - b)))
+
+
+def muca_comparison(torch, mcs, ctx, sizes, prod_max):
+    """Learned vs plain initial weights: train on the method's converged
+    weights at L = 16, 24, 32, 48, compare total sweeps to a flat histogram at
+    the test sizes, then the same production run in both arms, scored against
+    the exact g(E)."""
+    import numpy as np  # noqa: F401
+
+    from paper_1709_04394_amd import learned_muca as lm
+
+    t0 = time.perf_counter()
+    lnW_by_L, runs = lm.training_weights(ctx)
+    train = {str(L): {"iterations": r["iterations"], "total_sweeps": r["total_sweeps"],
+                      "seconds": round(r["seconds"], 2)} for L, r in runs.items()}
+    params, log = lm.train_network(ctx, lnW_by_L)
+    out = {"walkers": lm.WALKERS, "train_sizes": list(lm.TRAIN_L), "training_runs": train,
+           "mlp": {"epochs": int(log.size), "loss_first": float(log[0]), "loss_last": float(log[-1])},
+           "schedule": "hot walker starts thermalised by %d canonical sweeps at the initial weights' -dlnW/dE "
+                       "(16 groups; flat weights: none needed); iterations of 2 unrecorded + R recorded sweeps, "
+                       "R = 10 doubled up to %s after every iteration that reached the whole window without "
+                       "improving the previous flatness; flat = min/max >= 0.8"
+                       % (lm.PREP_SWEEPS, {L: lm.REC_MAX[L] for L in sizes}), "sizes": {}}
+    for L in sizes:
+        prod = max(2000, prod_max * L * L // (128 * 128))
+        c = lm.compare(ctx, L, params, prod_sweeps=prod)
+        ex = exact_lng(L)
+        row = {"prod_sweeps_per_walker": prod}
+        for arm in ("plain", "learned"):
+            r = c[arm]
+            row[arm] = {"converged": bool(r["converged"]), "iterations": int(r["iterations"]),
+                        "sweeps_per_walker": int(r["sweeps_per_walker"]), "total_sweeps": int(r["total_sweeps"]),
+                        "prep_sweeps_per_walker": int(r["prep_sweeps_per_walker"]),
+                        "seconds": round(r["seconds"], 2), "final_min_over_max": round(float(r["min_over_max"]), 4),
+                        "max_abs_lng_error": lng_error(r["lng"], ex) if r["lng"] is not None else None}
+        row["learned"]["fallback"] = bool(c["learned"]["fallback"])
+        init_err = lng_error(-c["lnW_init"], ex)
+        row["learned"]["initial_max_abs_lnW_error"] = init_err
+        pl, le = row["plain"], row["learned"]
+        row["sweeps_ratio_learned_over_plain"] = (le["sweeps_per_walker"] / pl["sweeps_per_walker"]
+                                                  if pl["converged"] and le["converged"] else None)
+        out["sizes"][str(L)] = row
+        print(json.dumps({"muca_progress": L, "row": row}), file=sys.stderr, flush=True)
+    out["seconds"] = round(time.perf_counter() - t0, 1)
+    return out
 
 
 def copy_probe():
@@ -206,6 +367,10 @@ def main():
                                   "beta in {0.40, beta_c, 0.50}, per-sweep E and M",
                       "L": L, "lattices": 3, "betas": list(BETAS), "sweeps_per_step": SWEEPS_PER_STEP},
            "roofline": roof}
+    if not a.no_rows:
+        out["rows"] = row_measurements(torch, mcs, ctx, dev)
+    if a.muca:
+        out["muca"] = muca_comparison(torch, mcs, ctx, [int(x) for x in a.muca.split(",")], a.muca_prod)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out))

@@ -143,12 +143,14 @@ int mc_sweep_betas(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *
 int mc_measure(mc_ctx *ctx, const mc_geom *geom, const void *spins, const int8_t *J, int64_t *EM,
                void *stream);
 
-/* Launch shape of the fused 2D sweep (int8, J = 1, Metropolis, Lx a multiple
- * of 64): band height H (rows per workgroup), K sweeps per launch and threads
- * per workgroup.  The shape changes speed only, never results (the
- * determinism contract above).  mc_set_tile_plan fixes it for the geometry's
- * (Lx, Ly, count) on this context; mc_get_tile_plan reports the shape in use
- * (the tuned or set one, else a default).  Host-only calls.                 */
+/* Launch shape of the fused sweeps (int8, Lx a multiple of 64; 2D: J = 1,
+ * Metropolis; 3D: Metropolis or heat-bath, with or without couplings): band
+ * height H (2D rows per workgroup) or tile side H (3D: H x H rows in y, z),
+ * K sweeps per launch and threads per workgroup.  The shape changes speed
+ * only, never results (the determinism contract above).  mc_set_tile_plan
+ * fixes it for the geometry (dims, extents, count) on this context;
+ * mc_get_tile_plan reports the shape in use (the tuned or set one, else a
+ * default).  Host-only calls.                                               */
 int mc_set_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t H, int32_t K, int32_t threads);
 int mc_get_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t *H, int32_t *K, int32_t *threads);
 
@@ -160,6 +162,10 @@ int mc_get_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t *H, int32_t *K, i
  * Synchronises the stream.                                                 */
 int mc_tune_sweep(mc_ctx *ctx, const mc_geom *geom, void *scratch_a, void *scratch_b, double beta,
                   int32_t sweeps, void *stream);
+/* As mc_tune_sweep for the given update rule (MC_METROPOLIS or MC_HEATBATH);
+ * 3D geometries (Lx a multiple of 64) are tuned for tiles of H x H rows.  */
+int mc_tune_sweep_rule(mc_ctx *ctx, const mc_geom *geom, int32_t rule, void *scratch_a, void *scratch_b,
+                       double beta, int32_t sweeps, void *stream);
 
 /* ------------------------------------------------------------------------
  * Population annealing (Sec. "Population annealing", Eq. Q) of npop
@@ -222,10 +228,19 @@ int mc_pa_anneal(mc_ctx *ctx, const mc_pa_args *args, void *const *pop_spins, do
  * attempted move.  L in {4, 8, 12, 16, 24, 32, 48, 64, 96, 128}.            */
 size_t mc_muca_workspace_bytes(int32_t L, int32_t walkers);
 
-/* Walker start: hot start of walker w keyed by replica id w; if its energy is
- * above the window the odd sub-lattice is flipped (E -> -E).
- * spins: device int8 [walkers][L^2]; E: device int64 [walkers].  Stream-ordered. */
-int mc_muca_start(mc_ctx *ctx, int32_t L, int32_t walkers, uint64_t seed, int8_t *spins, int64_t *E, void *stream);
+/* Walker starts.  MC_MUCA_HOT: walker w is the hot start of replica id w.
+ * MC_MUCA_STRATIFIED: site i of walker w of W is -1 iff byte (i mod 16) of
+ * Philox(ctr = (i/16, w, 0, TAG_INIT << 24)) is >= 256 - c_w, where c_w is
+ * the largest c in 0..128 with (257 - 2c)^2 2W > 65536 (2W - 2w - 1), i.e.
+ * 128 (1 - sqrt(1 - (w + 1/2)/W)) rounded: the expected starting energies
+ * -2N (1 - c_w/128)^2 spread evenly over the window (c_w = 128 is the hot
+ * start).  The paper leaves the walkers' initial states open.  Either way,
+ * a walker whose energy is above the window has its odd sub-lattice flipped
+ * (E -> -E).  spins: device int8 [walkers][L^2]; E: device int64 [walkers].
+ * Stream-ordered.                                                          */
+enum { MC_MUCA_HOT = 0, MC_MUCA_STRATIFIED = 1 };
+int mc_muca_start(mc_ctx *ctx, int32_t L, int32_t walkers, uint64_t seed, int32_t start, int8_t *spins, int64_t *E,
+                  void *stream);
 
 /* nsweeps multicanonical sweeps of every walker at weights lnW (host
  * [N/2 + 1], finite), sweep numbers sweep0.., updating spins and E in place;
@@ -243,6 +258,23 @@ typedef struct {
     int32_t prod_sweeps;  /* production sweeps at the final weights             */
     double flat;          /* flatness criterion min/max over reachable levels   */
     uint64_t seed;
+    int32_t start;        /* MC_MUCA_HOT or MC_MUCA_STRATIFIED walker starts    */
+    int32_t rec_max;      /* recorded sweeps double, up to this, after every
+                             iteration whose histogram reached every window
+                             level (<= rec_sweeps: fixed length)              */
+    int32_t eq_scale;     /* unrecorded sweeps per iteration: eq_sweeps +
+                             eq_scale * (recorded sweeps of that iteration)   */
+    int32_t prep_sweeps;  /* > 0: after the start, walker group g of 16 runs
+                             this many canonical Metropolis sweeps (replica id
+                             = walker, sweeps 0..) at the initial weights'
+                             inverse temperature -d lnW/dE (central difference
+                             around level round((g + 1/2) N / 32), at least 0;
+                             flat weights: 0); energies are then recomputed and
+                             walkers above the window flipped (E -> -E)       */
+    int32_t rec_rule;     /* 0: double the recorded sweeps after every
+                             iteration that reached every window level; 1:
+                             only when such an iteration's flatness did not
+                             improve on the previous iteration's             */
 } mc_muca_args;
 
 typedef struct {
@@ -251,8 +283,13 @@ typedef struct {
     double min_over_max;        /* flatness of the last iteration             */
 } mc_muca_stats;
 
-/* The whole method: walker start, iterations of eq_sweeps + rec_sweeps with
- * the plain recursion ln W -= ln H (H > 0; then ln W at E = 0 set to 0) until
+/* The whole method: walker start, iterations of eq_sweeps + eq_scale R
+ * unrecorded and R recorded sweeps (the paper lets walkers thermalise to the
+ * updated weights before each iteration's statistics; R = rec_sweeps, doubled
+ * up to rec_max after every iteration that
+ * visited every window level but k = 1; the paper leaves iteration lengths
+ * open) with the plain recursion ln W -= ln H (H > 0; then ln W at E = 0 set
+ * to 0) until
  * min/max of H over all window levels but k = 1 reaches flat, then
  * prod_sweeps at fixed weights; ln g = ln H_prod - ln W (-inf where empty).
  * lnW_init: host [N/2 + 1] initial ln W, or NULL for flat weights.
@@ -292,13 +329,36 @@ typedef struct {
 } mc_mlp_args;
 
 /* epochs full-batch Adam steps on params (in/out); loss_log: device float
- * [epochs], the loss before each step.  All epochs run as one captured
- * hipGraph; blocking.                                                      */
+ * [epochs], the loss before each step.  Epochs run as a captured hipGraph of
+ * up to 500 epochs, replayed; blocking.                                    */
 int mc_mlp_train(mc_ctx *ctx, const mc_mlp_args *args, const float *X, const float *Y, int32_t n, float *params,
                  float *loss_log, void *ws, size_t ws_bytes, void *stream);
 
 /* Y = network(X) for n samples.  Stream-ordered.                           */
 int mc_mlp_predict(mc_ctx *ctx, const float *params, const float *X, int32_t n, float *Y, void *stream);
+
+/* Training set from converged multicanonical weights (Sec. "Multicanonical
+ * simulations": the weights the recursion of Eq. weight_modification
+ * produced at smaller L): for each lattice size Ls[i] (even, >= 4) and every
+ * level k = 0 .. N/2 of the window E = 4k - 2N in [-2N, 0] except the empty
+ * level k = 1, one sample x = (E/N + 1, 32/L - 1), y = -(lnW[k] - lnW[N/2]) / N,
+ * computed in FP64 and rounded to FP32.  lnW: host array of nL pointers to
+ * N/2 + 1 doubles each (finite except at k = 1).  X: host float [cap][2],
+ * Y: host float [cap]; *n_out = samples written.  MC_E_RANGE if they do not
+ * fit in cap or a weight is not finite.  Host-only call.                   */
+int mc_mlp_training_set(mc_ctx *ctx, int32_t nL, const int32_t *Ls, const double *const *lnW, float *X, float *Y,
+                        int32_t cap, int32_t *n_out);
+
+/* Initial log-weights of an L x L lattice from a trained network: the inputs
+ * of every window level are formed on the device, the network runs as in
+ * mc_mlp_predict, and lnW_out[k] = -N y(k) (FP64, host array of N/2 + 1),
+ * shifted so that lnW_out[N/2] = 0.  If any prediction is not finite the
+ * plain method's flat start is returned instead (all zeros) and
+ * *used_fallback = 1, else 0.  ws: device scratch of
+ * mc_mlp_lnw_workspace_bytes(L).  Blocking.                                */
+size_t mc_mlp_lnw_workspace_bytes(int32_t L);
+int mc_mlp_lnw_init(mc_ctx *ctx, const float *params, int32_t L, double *lnW_out, int32_t *used_fallback, void *ws,
+                    size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

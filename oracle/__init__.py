@@ -80,7 +80,9 @@ def lib():
                                    ctypes.c_int, ctypes.c_uint64, u8p, u8p, u8p, u8p, u8p, u8p]
         L.orc_muca_table.argtypes = [ctypes.c_int, u8p, u8p]
         L.orc_muca_table.restype = None
-        L.orc_muca_start.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, u8p, u8p]
+        L.orc_muca_start.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, u8p, u8p]
+        L.orc_muca_strat_level.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.orc_muca_settle.argtypes = [ctypes.c_int, ctypes.c_int, u8p, u8p]
         L.orc_muca_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, u8p, u8p, u8p, ctypes.c_uint64,
                                       ctypes.c_uint64, ctypes.c_int, ctypes.c_int, u8p]
         _lib = L
@@ -255,11 +257,18 @@ def muca_table(L, lnW):
     return T
 
 
-def muca_start(L, walkers, seed):
+MUCA_HOT, MUCA_STRATIFIED = 0, 1
+
+
+def muca_strat_level(w, walkers):
+    return lib().orc_muca_strat_level(w, walkers)
+
+
+def muca_start(L, walkers, seed, start=MUCA_HOT):
     N = L * L
     spins = np.zeros(walkers * N, dtype=np.int8)
     E = np.zeros(walkers, dtype=np.int64)
-    _check(lib().orc_muca_start(L, walkers, seed, _p(spins), _p(E)), "muca_start")
+    _check(lib().orc_muca_start(L, walkers, seed, start, _p(spins), _p(E)), "muca_start")
     return spins, E
 
 
@@ -299,28 +308,79 @@ def muca_update(L, lnW, H):
     return out
 
 
-def muca_run(L, walkers, seed, eq_sweeps, rec_sweeps, max_iter, prod_sweeps, flat=0.8, lnW_init=None):
+MUCA_PREP_GROUPS = 16
+
+
+def muca_prep_betas(L, walkers, lnW):
+    """Inverse temperature of each preparation group: the slope -d ln W / dE
+    of the initial weights (central difference, dE = 8 between levels k - 1
+    and k + 1) at the group's target level k_g = round((g + 1/2) K / G),
+    clamped to 2 .. K - 1, and at least 0.  Flat weights give 0 everywhere."""
+    K = muca_levels(L) - 1
+    G = min(MUCA_PREP_GROUPS, walkers)
+    out = []
+    for g in range(G):
+        k = ((2 * g + 1) * K + G) // (2 * G)
+        k = min(max(k, 2), K - 1)
+        out.append(max(0.0, -(float(lnW[k + 1]) - float(lnW[k - 1])) / 8.0))
+    return out
+
+
+def muca_prepare(L, spins, E, seed, lnW, prep_sweeps):
+    """Walkers thermalised to the initial weights: walker group g (walkers
+    g W / G .. (g + 1) W / G - 1) runs prep_sweeps canonical Metropolis sweeps
+    at muca_prep_betas()[g] (replica id = walker, sweeps 0 ..), then every
+    walker's energy is recomputed and a walker above the window has its odd
+    sub-lattice flipped."""
+    walkers = E.size
+    N = L * L
+    G = min(MUCA_PREP_GROUPS, walkers)
+    betas = muca_prep_betas(L, walkers, lnW)
+    for g in range(G):
+        for w in range(g * walkers // G, (g + 1) * walkers // G):
+            s = spins[w * N:(w + 1) * N]
+            sweep(2, L, s, betas[g], seed, w, 0, prep_sweeps, record=False)
+    _check(lib().orc_muca_settle(L, walkers, _p(spins), _p(E)), "muca_settle")
+
+
+def muca_run(L, walkers, seed, eq_sweeps, rec_sweeps, max_iter, prod_sweeps, flat=0.8, lnW_init=None,
+             start=MUCA_HOT, rec_max=0, eq_scale=0, prep_sweeps=0, rec_rule=0):
     """Parallel-walker multicanonical iteration: every walker shares W; the
     histograms of all walkers are added; the weights follow the plain recursion
     until the histogram is flat (min/max over reachable levels >= flat); then a
-    production run at fixed weights gives ln g = ln H - ln W."""
+    production run at fixed weights gives ln g = ln H - ln W.  Iteration
+    length: rec_sweeps recorded sweeps, doubled (up to rec_max) after every
+    iteration whose histogram reached every level of the window (rec_rule 0)
+    or after every such iteration whose flatness did not improve on the
+    previous one (rec_rule 1); each iteration first runs eq_sweeps + eq_scale * R
+    unrecorded sweeps.  prep_sweeps > 0 thermalises the walkers to the initial
+    weights first (muca_prepare)."""
     K = muca_levels(L)
     lnW = np.zeros(K) if lnW_init is None else np.array(lnW_init, dtype=np.float64)
-    spins, E = muca_start(L, walkers, seed)
+    spins, E = muca_start(L, walkers, seed, start)
+    if prep_sweeps > 0:
+        muca_prepare(L, spins, E, seed, lnW, prep_sweeps)
+    reach = muca_flat_levels(L)
     sweep = 0
-    it, converged, ratio = 0, False, 0.0
+    it, converged, ratio, prev = 0, False, 0.0, 0.0
+    R = rec_sweeps
     history = []
     while it < max_iter:
-        muca_sweeps(L, spins, E, lnW, seed, sweep, eq_sweeps, False)
-        sweep += eq_sweeps
-        H = muca_sweeps(L, spins, E, lnW, seed, sweep, rec_sweeps, True)
-        sweep += rec_sweeps
+        neq = eq_sweeps + eq_scale * R
+        muca_sweeps(L, spins, E, lnW, seed, sweep, neq, False)
+        sweep += neq
+        H = muca_sweeps(L, spins, E, lnW, seed, sweep, R, True)
+        sweep += R
         it += 1
         ratio = muca_flatness(L, H)
         history.append(ratio)
         if ratio >= flat:
             converged = True
             break
+        covered = bool(np.all(H[reach] > 0))
+        if covered and (rec_rule == 0 or ratio <= prev):
+            R = min(2 * R, max(rec_max, rec_sweeps))
+        prev = ratio if covered else 0.0
         lnW = muca_update(L, lnW, H)
     Hp = muca_sweeps(L, spins, E, lnW, seed, sweep, prod_sweeps, True) if prod_sweeps > 0 else None
     lng = None

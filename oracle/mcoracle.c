@@ -501,7 +501,54 @@ void orc_muca_table(int L, const double *lnW, uint64_t *T)
 
 /* Walker start: hot start keyed by the walker index; if its energy lies above
  * the window, flip the spins of the odd sub-lattice, which maps E to -E.     */
-int orc_muca_start(int L, int walkers, uint64_t seed, int8_t *spins, int64_t *E)
+/* Level of disorder of walker w of W in the stratified start: the largest
+ * c in 0..128 with (257 - 2c)^2 * 2W > 65536 (2W - 2w - 1), i.e.
+ * c = 128 (1 - sqrt(1 - (w + 1/2)/W)) rounded to the nearest integer, in
+ * integer arithmetic.  Flipping each spin of the ground state with
+ * probability c/256 gives E ~ -2N (1 - c/128)^2, so the walkers' starting
+ * energies spread evenly over the window [-2N, 0].                            */
+int orc_muca_strat_level(int w, int W)
+{
+    int c = 0;
+    for (int t = 1; t <= 128; ++t) {
+        int64_t a = (int64_t)(257 - 2 * t) * (257 - 2 * t) * 2 * (int64_t)W;
+        int64_t b = (int64_t)65536 * (2 * (int64_t)W - 2 * (int64_t)w - 1);
+        if (a > b) c = t;
+    }
+    return c;
+}
+
+/* Walker starts.  start 0 (hot): walker w is the hot start of replica id w.
+ * start 1 (stratified): site i of walker w is -1 iff byte (i mod 16) of
+ * Philox(INIT, i/16, w) is at least 256 - c_w (c_w = 128 is the hot start).
+ * Either way the odd sub-lattice is flipped when E > 0 (E -> -E), so every
+ * walker starts inside the window.                                           */
+int orc_muca_start(int L, int walkers, uint64_t seed, int start, int8_t *spins, int64_t *E)
+{
+    if (L < 4 || (L & 1) || walkers < 1 || start < 0 || start > 1) return -1;
+    int64_t N = (int64_t)L * L;
+    #pragma omp parallel for schedule(static)
+    for (int64_t w = 0; w < walkers; ++w) {
+        int8_t *s = spins + w * N;
+        int64_t e, m;
+        unsigned c = start ? (unsigned)orc_muca_strat_level((int)w, walkers) : 128u;
+        for (int64_t i = 0; i < N; ++i)
+            s[i] = orc_draw_byte(seed, ORC_TAG_INIT, (uint32_t)i, (uint32_t)w, 0, 0) >= 256u - c ? -1 : 1;
+        orc_measure(2, L, L, 1, s, NULL, &e, &m);
+        if (e > 0) {
+            for (int y = 0; y < L; ++y)
+                for (int x = 0; x < L; ++x)
+                    if ((x + y) & 1) s[x + (int64_t)L * y] = (int8_t)-s[x + (int64_t)L * y];
+            orc_measure(2, L, L, 1, s, NULL, &e, &m);
+        }
+        E[w] = e;
+    }
+    return 0;
+}
+
+/* Energies of given walker lattices; a walker above the window has its odd
+ * sub-lattice flipped (E -> -E).                                            */
+int orc_muca_settle(int L, int walkers, int8_t *spins, int64_t *E)
 {
     if (L < 4 || (L & 1) || walkers < 1) return -1;
     int64_t N = (int64_t)L * L;
@@ -509,13 +556,12 @@ int orc_muca_start(int L, int walkers, uint64_t seed, int8_t *spins, int64_t *E)
     for (int64_t w = 0; w < walkers; ++w) {
         int8_t *s = spins + w * N;
         int64_t e, m;
-        orc_init(2, L, L, 1, s, 1, seed, (uint32_t)w);
         orc_measure(2, L, L, 1, s, NULL, &e, &m);
         if (e > 0) {
             for (int y = 0; y < L; ++y)
                 for (int x = 0; x < L; ++x)
                     if ((x + y) & 1) s[x + (int64_t)L * y] = (int8_t)-s[x + (int64_t)L * y];
-            orc_measure(2, L, L, 1, s, NULL, &e, &m);
+            e = -e;
         }
         E[w] = e;
     }

@@ -105,22 +105,26 @@ def train(p, X, Y, epochs, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 def training_set(lnW_by_L):
-    """(X, Y) from converged ln W per L: every window level but k = 1."""
+    """(X, Y) from converged ln W per L: every window level but k = 1, with
+    ln W taken relative to its value at E = 0 (level N/2)."""
     X, Y = [], []
     for L, lnW in sorted(lnW_by_L.items()):
         N = L * L
         K = N // 2
+        lnW = np.asarray(lnW, dtype=np.float64)
         k = np.array([i for i in range(K + 1) if i != 1])
         E = 4 * k - 2 * N
         X.append(features(E, N, L))
-        Y.append(-np.asarray(lnW, dtype=np.float64)[k] / N)
+        Y.append(-(lnW[k] - lnW[K]) / N)
     return np.concatenate(X), np.concatenate(Y)
 
 
 def predict_lnW(p, L):
-    """Initial ln W(E) = -N * y(E/N, 1/L) over the window levels."""
+    """Initial ln W(E) = -N * y(E/N, 1/L) over the window levels, shifted to
+    ln W(0) = 0."""
     N = L * L
     K = N // 2
     E = 4 * np.arange(K + 1) - 2 * N
     y, _ = forward(p, features(E, N, L))
-    return -N * y
+    lnW = -N * y
+    return lnW - lnW[K]

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libmcspin.so")
 INT8, MSC64 = 0, 1
 METROPOLIS, HEATBATH = 0, 1
 COLD, HOT = 0, 1
+MUCA_HOT, MUCA_STRATIFIED = 0, 1
 
 MC_OK, MC_E_INVAL, MC_E_SHAPE, MC_E_RANGE, MC_E_LAYOUT, MC_E_WORKSPACE, MC_E_DEVICE, MC_E_NOTCONV = \
     0, -1, -2, -3, -4, -5, -6, -7
@@ -60,7 +61,9 @@ class PAArgs(ctypes.Structure):
 class MucaArgs(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("walkers", ctypes.c_int32), ("eq_sweeps", ctypes.c_int32),
                 ("rec_sweeps", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("prod_sweeps", ctypes.c_int32),
-                ("flat", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("flat", ctypes.c_double), ("seed", ctypes.c_uint64), ("start", ctypes.c_int32),
+                ("rec_max", ctypes.c_int32), ("eq_scale", ctypes.c_int32), ("prep_sweeps", ctypes.c_int32),
+                ("rec_rule", ctypes.c_int32)]
 
 
 class MucaStats(ctypes.Structure):
@@ -106,15 +109,24 @@ _lib_fns = dict(
                                                          _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     mc_tune_sweep=_sig("mc_tune_sweep", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _c.c_double, _c.c_int32,
                                                    _vp]),
+    mc_tune_sweep_rule=_sig("mc_tune_sweep_rule", _c.c_int, [_vp, _c.POINTER(Geom), _c.c_int32, _vp, _vp,
+                                                             _c.c_double, _c.c_int32, _vp]),
     mc_mlp_param_count=_sig("mc_mlp_param_count", _c.c_int32, []),
     mc_mlp_workspace_bytes=_sig("mc_mlp_workspace_bytes", _c.c_size_t, [_c.c_int32]),
+    mc_mlp_training_set=_sig("mc_mlp_training_set", _c.c_int,
+                             [_vp, _c.c_int32, _c.POINTER(_c.c_int32), _c.POINTER(_c.POINTER(_c.c_double)),
+                              _c.POINTER(_c.c_float), _c.POINTER(_c.c_float), _c.c_int32, _c.POINTER(_c.c_int32)]),
+    mc_mlp_lnw_workspace_bytes=_sig("mc_mlp_lnw_workspace_bytes", _c.c_size_t, [_c.c_int32]),
+    mc_mlp_lnw_init=_sig("mc_mlp_lnw_init", _c.c_int, [_vp, _vp, _c.c_int32, _c.POINTER(_c.c_double),
+                                                         _c.POINTER(_c.c_int32), _vp, _c.c_size_t, _vp]),
     mc_mlp_init=_sig("mc_mlp_init", _c.c_int, [_vp, _vp, _c.c_uint64, _vp]),
     mc_mlp_grad=_sig("mc_mlp_grad", _c.c_int, [_vp, _vp, _vp, _vp, _c.c_int32, _vp, _vp, _vp, _c.c_size_t, _vp]),
     mc_mlp_train=_sig("mc_mlp_train", _c.c_int, [_vp, _c.POINTER(MlpArgs), _vp, _vp, _c.c_int32, _vp, _vp, _vp,
                                                  _c.c_size_t, _vp]),
     mc_mlp_predict=_sig("mc_mlp_predict", _c.c_int, [_vp, _vp, _vp, _c.c_int32, _vp, _vp]),
     mc_muca_workspace_bytes=_sig("mc_muca_workspace_bytes", _c.c_size_t, [_c.c_int32, _c.c_int32]),
-    mc_muca_start=_sig("mc_muca_start", _c.c_int, [_vp, _c.c_int32, _c.c_int32, _c.c_uint64, _vp, _vp, _vp]),
+    mc_muca_start=_sig("mc_muca_start", _c.c_int, [_vp, _c.c_int32, _c.c_int32, _c.c_uint64, _c.c_int32, _vp, _vp,
+                                                   _vp]),
     mc_muca_sweeps=_sig("mc_muca_sweeps", _c.c_int, [_vp, _c.c_int32, _c.c_int32, _vp, _vp, _c.POINTER(_c.c_double),
                                                      _c.c_uint64, _c.c_uint64, _c.c_int32, _c.c_int32, _vp, _vp,
                                                      _c.c_size_t, _vp]),
@@ -315,6 +327,41 @@ class Context:
                     "mc_mlp_predict")
         return Y
 
+    def mlp_training_set(self, lnW_by_L):
+        """(X, Y) host float32 arrays from converged ln W per L (dict L -> array
+        of N/2 + 1 doubles), as mc_mlp_training_set builds them."""
+        import numpy as np
+
+        Ls = sorted(lnW_by_L)
+        arrs = [np.ascontiguousarray(lnW_by_L[L], dtype=np.float64) for L in Ls]
+        cap = sum(L * L // 2 for L in Ls)
+        X = np.zeros((max(cap, 1), 2), dtype=np.float32)
+        Y = np.zeros(max(cap, 1), dtype=np.float32)
+        n = ctypes.c_int32()
+        Larr = (ctypes.c_int32 * len(Ls))(*Ls)
+        parr = (ctypes.POINTER(ctypes.c_double) * len(Ls))(
+            *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrs])
+        fp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        self._check(_lib.mc_mlp_training_set(self._h, len(Ls), Larr, parr, fp(X), fp(Y), cap, ctypes.byref(n)),
+                    "mc_mlp_training_set")
+        return X[:n.value], Y[:n.value]
+
+    def mlp_lnw_init(self, params, L):
+        """Initial ln W (host float64, N/2 + 1 levels) of an L x L lattice from
+        a trained network, and whether the flat fallback was used."""
+        import numpy as np
+
+        out = np.zeros(L * L // 2 + 1, dtype=np.float64)
+        fb = ctypes.c_int32()
+        nb = int(_lib.mc_mlp_lnw_workspace_bytes(L))
+        if nb == 0:
+            raise MCError(MC_E_SHAPE, "unsupported L=%d" % L)
+        ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        self._check(_lib.mc_mlp_lnw_init(self._h, _ptr(params), L,
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(fb),
+                                         _ptr(ws), ws.numel(), _stream(self.device)), "mc_mlp_lnw_init")
+        return out, bool(fb.value)
+
     # ----------------------------------------------------------- multicanonical
     def muca_workspace(self, L, walkers):
         n = int(_lib.mc_muca_workspace_bytes(L, walkers))
@@ -322,11 +369,11 @@ class Context:
             raise MCError(MC_E_SHAPE, "unsupported L=%d or walkers=%d" % (L, walkers))
         return torch.empty(n, dtype=torch.uint8, device=self.device)
 
-    def muca_start(self, L, walkers, seed, spins=None, E=None):
+    def muca_start(self, L, walkers, seed, spins=None, E=None, start=0):
         spins = torch.empty((walkers, L * L), dtype=torch.int8, device=self.device) if spins is None else spins
         E = torch.empty(walkers, dtype=torch.int64, device=self.device) if E is None else E
-        self._check(_lib.mc_muca_start(self._h, L, walkers, seed, _ptr(spins), _ptr(E), _stream(self.device)),
-                    "mc_muca_start")
+        self._check(_lib.mc_muca_start(self._h, L, walkers, seed, start, _ptr(spins), _ptr(E),
+                                       _stream(self.device)), "mc_muca_start")
         return spins, E
 
     def muca_sweeps(self, L, spins, E, lnW, seed, sweep0, nsweeps, record, H=None, ws=None):
@@ -341,14 +388,15 @@ class Context:
                     "mc_muca_sweeps")
 
     def muca_run(self, L, walkers, seed, eq_sweeps, rec_sweeps, max_iter, prod_sweeps, flat=0.8, lnW_init=None,
-                 spins=None, ws=None):
+                 spins=None, ws=None, start=0, rec_max=0, eq_scale=0, prep_sweeps=0, rec_rule=0):
         """Full multicanonical run; returns a dict like oracle.muca_run."""
         import numpy as np
 
         K1 = L * L // 2 + 1
         spins = torch.empty((walkers, L * L), dtype=torch.int8, device=self.device) if spins is None else spins
         ws = self.muca_workspace(L, walkers) if ws is None else ws
-        a = MucaArgs(L, walkers, eq_sweeps, rec_sweeps, max_iter, prod_sweeps, float(flat), seed)
+        a = MucaArgs(L, walkers, eq_sweeps, rec_sweeps, max_iter, prod_sweeps, float(flat), seed, start, rec_max,
+                     eq_scale, prep_sweeps, rec_rule)
         init = None
         if lnW_init is not None:
             init = np.ascontiguousarray(lnW_init, dtype=np.float64)
@@ -377,7 +425,7 @@ class Context:
                                           ctypes.byref(T)), "mc_get_tile_plan")
         return H.value, K.value, T.value
 
-    def tune_sweep(self, geom, scratch_a, scratch_b, beta, sweeps=20):
-        self._check(_lib.mc_tune_sweep(self._h, ctypes.byref(geom), _ptr(scratch_a), _ptr(scratch_b), float(beta),
-                                       sweeps, _stream(self.device)), "mc_tune_sweep")
+    def tune_sweep(self, geom, scratch_a, scratch_b, beta, sweeps=20, rule=METROPOLIS):
+        self._check(_lib.mc_tune_sweep_rule(self._h, ctypes.byref(geom), rule, _ptr(scratch_a), _ptr(scratch_b),
+                                            float(beta), sweeps, _stream(self.device)), "mc_tune_sweep_rule")
         return self.get_tile_plan(geom)

@@ -257,7 +257,8 @@ int mc_sweep_betas(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *
     c.tab = tabs[0];
     c.per_lattice = 1;
     c.tabs = tabs.data();
-    if (tile2d_supported(c, MC_INT8) && ws && ws_bytes >= fused_workspace_bytes(c.g, MC_INT8))
+    if ((tile2d_supported(c, MC_INT8) || tile3d_supported(c, MC_INT8)) && ws &&
+        ws_bytes >= fused_workspace_bytes(c.g, MC_INT8))
         return run_sweeps(ctx, c, MC_INT8, spins, a1.sweep0, a1.nsweeps, EM, em_stride, ws, ws_bytes, s);
     // otherwise one lattice at a time
     for (int l = 0; l < geom->count; ++l) {

@@ -12,8 +12,9 @@
 
 namespace mcs {
 
-// Launch shape of the fused 2D sweep: band height, sweeps per launch and
-// threads per workgroup.  Any choice gives the same results.
+// Launch shape of the fused sweeps: band height (2D) or tile side in y and z
+// (3D), sweeps per launch and threads per workgroup.  Any choice gives the
+// same results.
 struct TilePlan {
     int H = 16;
     int K = 2;
@@ -25,8 +26,8 @@ struct TilePlan {
 struct mc_ctx {
     int device = 0;
     std::string last_error;
-    // tuned launch shapes keyed by (Lx, Ly, count)
-    std::map<std::tuple<int, int, int>, mcs::TilePlan> tile_plans;
+    // tuned launch shapes keyed by (dims, Lx, Ly, Lz, count)
+    std::map<std::tuple<int, int, int, int, int>, mcs::TilePlan> tile_plans;
     // stream on which launch sequences are recorded into hipGraphs (created
     // on first use, default priority, destroyed with the context)
     hipStream_t capture = nullptr;
@@ -56,6 +57,19 @@ hipError_t launch_tile2d(const SweepCall &c, const void *src, int in_packed, voi
                          uint64_t sweep0, int k, int H, int threads, int64_t *EM, int64_t em_stride, int64_t em_sweep0,
                          hipStream_t s);
 TilePlan default_tile_plan(const Geom &g);
+
+// fused 3D kernel (k_tile3d.hip)
+bool tile3d_supported(const SweepCall &c, int layout);
+size_t tile3d_lds_bytes(int Lx, int H, int K, bool hasJ);
+hipError_t launch_tile3d(const SweepCall &c, const void *src, int in_packed, void *dst, int out_packed,
+                         const uint32_t *Jp, uint64_t sweep0, int k, int H, int threads, int64_t *EM,
+                         int64_t em_stride, int64_t em_sweep0, hipStream_t s);
+hipError_t launch_pack_couplings(const Geom &g, const int8_t *J, uint32_t *Jp, hipStream_t s);
+
+// 64-lane multi-spin-coded half-sweep with fused per-lane E, M (k_msc.hip)
+bool msc_fast_supported(const SweepCall &c, int layout);
+hipError_t launch_msc_phase(const SweepCall &c, uint64_t *words, uint64_t sweep, int phase, int64_t *EM,
+                            hipStream_t s);
 
 // Sweep driver: chooses the fused kernel when the geometry and the workspace
 // allow it, the generic two-launch half-sweeps otherwise.

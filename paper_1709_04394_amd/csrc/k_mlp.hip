@@ -196,6 +196,25 @@ hipError_t launch_mlp_epoch(float *params, const float *X, const float *Y, int n
     return hipGetLastError();
 }
 
+// Inputs of the window levels k = 0 .. N/2 of an L x L lattice:
+// x = (E/N + 1, 32/L - 1) with E = 4k - 2N, in FP64 rounded to FP32.
+__global__ void k_mlp_features(int L, float *X)
+{
+    const int N = L * L, K = N / 2;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > K) return;
+    const double E = 4.0 * k - 2.0 * N;
+    X[2 * k] = (float)(E / (double)N + 1.0);
+    X[2 * k + 1] = (float)(32.0 / (double)L - 1.0);
+}
+
+hipError_t launch_mlp_features(int L, float *X, hipStream_t s)
+{
+    const int n = L * L / 2 + 1;
+    hipLaunchKernelGGL(k_mlp_features, dim3((n + 255) / 256), dim3(256), 0, s, L, X);
+    return hipGetLastError();
+}
+
 hipError_t launch_mlp_predict(const float *params, const float *X, int n, float *Y, hipStream_t s)
 {
     hipLaunchKernelGGL(k_mlp_predict, dim3((n + 127) / 128), dim3(128), 0, s, params, X, n, Y);

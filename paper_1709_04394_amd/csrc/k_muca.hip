@@ -12,6 +12,8 @@
 // update is a few bit operations, one LDS read and a compare.  Moves that
 // would leave the energy window [-2N, 0] are rejected and the current level
 // is counted again.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "muca.hpp"
 
@@ -206,10 +208,51 @@ hipError_t launch_muca_sweeps(const MucaArgs &a, int L, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_muca_start(int8_t *spins, int64_t *E, int L, int W, uint64_t seed, hipStream_t s)
+// Level of disorder of walker w of W in the stratified start: the largest c
+// in 0..128 with (257 - 2c)^2 * 2W > 65536 (2W - 2w - 1), i.e. 128 (1 -
+// sqrt(1 - (w + 1/2)/W)) rounded, found by bisection in integer arithmetic
+// (the condition is monotone in c).
+__device__ __forceinline__ uint32_t strat_level(int64_t w, int64_t W)
 {
-    Geom g{2, L, L, 1, (int64_t)L * L, W};
-    hipError_t e = launch_init_int8(g, spins, 1, seed, 0u, s);
+    int lo = 0, hi = 128;
+    const int64_t b = 65536ll * (2 * W - 2 * w - 1);
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t a = (int64_t)(257 - 2 * mid) * (257 - 2 * mid) * 2 * W;
+        if (a > b) lo = mid;
+        else hi = mid - 1;
+    }
+    return (uint32_t)lo;
+}
+
+// Walker lattices: site i of walker w is -1 iff byte (i mod 16) of
+// Philox(i/16, w, 0, TAG_INIT) >= 256 - c_w, c_w = 128 (hot start) or the
+// stratified level.  Threads: x = group of 16 sites, y strides over walkers.
+__global__ void k_muca_init(int8_t *spins, int L, int W, int stratified, uint32_t k0, uint32_t k1)
+{
+    const int N = L * L, groups = (N + 15) / 16;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= groups) return;
+    for (int w = blockIdx.y; w < W; w += gridDim.y) {
+        const uint32_t c = stratified ? strat_level(w, W) : 128u;
+        const uint4 b = philox(make_uint4((uint32_t)g, (uint32_t)w, 0u, ctr_w3(kTagInit, 0, 0)), k0, k1);
+        int8_t *s = spins + (int64_t)w * N;
+        for (int k = 0; k < 16 && 16 * g + k < N; ++k) s[16 * g + k] = byte_of(b, (uint32_t)k) >= 256u - c ? -1 : 1;
+    }
+}
+
+hipError_t launch_muca_settle(int8_t *spins, int64_t *E, int L, int W, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_muca_start, dim3((W + 63) / 64), dim3(64), 0, s, spins, E, L, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_muca_start(int8_t *spins, int64_t *E, int L, int W, uint64_t seed, int start, hipStream_t s)
+{
+    const int groups = (L * L + 15) / 16;
+    dim3 grid((unsigned)((groups + 255) / 256), (unsigned)std::min(W, 65535));
+    hipLaunchKernelGGL(k_muca_init, grid, dim3(256), 0, s, spins, L, W, start, (uint32_t)seed, (uint32_t)(seed >> 32));
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_muca_start, dim3((W + 63) / 64), dim3(64), 0, s, spins, E, L, W);
     return hipGetLastError();

@@ -19,5 +19,6 @@ hipError_t launch_mlp_epoch(float *params, const float *X, const float *Y, int n
                             int *step, float *loss_log, const MlpHyper &hp, hipStream_t s);
 hipError_t launch_mlp_predict(const float *params, const float *X, int n, float *Y, hipStream_t s);
 hipError_t launch_mlp_init(float *params, uint64_t seed, hipStream_t s);
+hipError_t launch_mlp_features(int L, float *X, hipStream_t s);
 
 }  // namespace mcs

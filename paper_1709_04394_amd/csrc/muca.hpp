@@ -20,6 +20,7 @@ struct MucaArgs {
 
 bool muca_L_supported(int L);
 hipError_t launch_muca_sweeps(const MucaArgs &a, int L, hipStream_t s);
-hipError_t launch_muca_start(int8_t *spins, int64_t *E, int L, int W, uint64_t seed, hipStream_t s);
+hipError_t launch_muca_start(int8_t *spins, int64_t *E, int L, int W, uint64_t seed, int start, hipStream_t s);
+hipError_t launch_muca_settle(int8_t *spins, int64_t *E, int L, int W, hipStream_t s);
 
 }  // namespace mcs

@@ -15,8 +15,10 @@ namespace {
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct MucaLayout {
-    size_t table = 0, hist = 0, H = 0, E = 0, total = 0;
+    size_t table = 0, hist = 0, H = 0, E = 0, prep = 0, prep_bytes = 0, total = 0;
 };
+
+constexpr int kPrepGroups = 16;  // walker groups of the preparation sweeps
 
 MucaLayout muca_layout(int L, int W)
 {
@@ -27,8 +29,24 @@ MucaLayout muca_layout(int L, int W)
     m.hist = off, off += align256(nb * nlev * 4);
     m.H = off, off += align256(nlev * 8);
     m.E = off, off += align256((size_t)W * 8);
+    // fused-sweep scratch for the largest preparation group
+    const int G = std::min(kPrepGroups, W);
+    Geom g{2, L, L, 1, (int64_t)L * L, (W + G - 1) / G};
+    m.prep_bytes = fused_workspace_bytes(g, MC_INT8);
+    m.prep = off, off += align256(m.prep_bytes);
     m.total = off;
     return m;
+}
+
+// Inverse temperature of preparation group g: -d ln W / dE of the initial
+// weights by the central difference over levels k_g - 1, k_g + 1 (dE = 8),
+// k_g = round((g + 1/2) K / G) clamped to 2 .. K - 1, and at least 0.
+double prep_beta(int L, int W, int g, const std::vector<double> &lnW)
+{
+    const int K = L * L / 2, G = std::min(kPrepGroups, W);
+    int k = ((2 * g + 1) * K + G) / (2 * G);
+    k = std::min(std::max(k, 2), K - 1);
+    return std::max(0.0, -(lnW[(size_t)k + 1] - lnW[(size_t)k - 1]) / 8.0);
 }
 
 // T[k][d] = ceil(min(1, exp(lnW[k+d] - lnW[k])) 2^32) (at least 1), stored as
@@ -118,14 +136,17 @@ size_t mc_muca_workspace_bytes(int32_t L, int32_t walkers)
     return muca_layout(L, walkers).total;
 }
 
-int mc_muca_start(mc_ctx *ctx, int32_t L, int32_t walkers, uint64_t seed, int8_t *spins, int64_t *E, void *stream)
+int mc_muca_start(mc_ctx *ctx, int32_t L, int32_t walkers, uint64_t seed, int32_t start, int8_t *spins, int64_t *E,
+                  void *stream)
 {
     if (!ctx) return MC_E_INVAL;
     int rc = check_LW(ctx, L, walkers);
     if (rc) return rc;
     if (!spins || !E) return fail(ctx, MC_E_INVAL, "spins or E is NULL");
+    if (start != MC_MUCA_HOT && start != MC_MUCA_STRATIFIED) return fail(ctx, MC_E_INVAL, "unknown start %d", start);
     if ((rc = set_device(ctx))) return rc;
-    return device_check(ctx, launch_muca_start(spins, E, L, walkers, seed, (hipStream_t)stream), "mc_muca_start");
+    return device_check(ctx, launch_muca_start(spins, E, L, walkers, seed, start, (hipStream_t)stream),
+                        "mc_muca_start");
 }
 
 int mc_muca_sweeps(mc_ctx *ctx, int32_t L, int32_t walkers, int8_t *spins, int64_t *E, const double *lnW,
@@ -161,6 +182,11 @@ int mc_muca_run(mc_ctx *ctx, const mc_muca_args *a, const double *lnW_init, int8
     if (a->eq_sweeps < 0 || a->rec_sweeps < 1 || a->max_iter < 0 || a->prod_sweeps < 0 || !(a->flat > 0.0) ||
         a->flat > 1.0)
         return fail(ctx, MC_E_RANGE, "sweep counts or flatness out of range");
+    if (a->start != MC_MUCA_HOT && a->start != MC_MUCA_STRATIFIED) return fail(ctx, MC_E_INVAL, "unknown start");
+    if (a->rec_max < 0 || a->rec_max > (1 << 24)) return fail(ctx, MC_E_RANGE, "rec_max out of range");
+    if (a->eq_scale < 0 || a->eq_scale > 64) return fail(ctx, MC_E_RANGE, "eq_scale out of range");
+    if (a->prep_sweeps < 0 || a->rec_rule < 0 || a->rec_rule > 1)
+        return fail(ctx, MC_E_RANGE, "prep_sweeps or rec_rule out of range");
     const int L = a->L, W = a->walkers, K = L * L / 2;
     const MucaLayout lay = muca_layout(L, W);
     if (!ws || ws_bytes < lay.total) return fail(ctx, MC_E_WORKSPACE, "workspace needs %zu bytes", lay.total);
@@ -174,21 +200,47 @@ int mc_muca_run(mc_ctx *ctx, const mc_muca_args *a, const double *lnW_init, int8
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
     int64_t *E = (int64_t *)(w + lay.E), *Hd = (int64_t *)(w + lay.H);
-    rc = device_check(ctx, launch_muca_start(spins, E, L, W, a->seed, s), "walker start");
+    rc = device_check(ctx, launch_muca_start(spins, E, L, W, a->seed, a->start, s), "walker start");
     if (rc) return rc;
+    if (a->prep_sweeps > 0) {
+        // walkers thermalised to the initial weights: group g runs canonical
+        // Metropolis sweeps at the weights' inverse temperature there
+        const int G = std::min(kPrepGroups, W);
+        for (int g = 0; g < G; ++g) {
+            const int w0 = (int)((int64_t)g * W / G), w1 = (int)((int64_t)(g + 1) * W / G);
+            SweepCall c;
+            c.g = Geom{2, L, L, 1, (int64_t)L * L, w1 - w0};
+            c.J = nullptr;
+            c.rule = MC_METROPOLIS;
+            c.seed_lo = (uint32_t)a->seed;
+            c.seed_hi = (uint32_t)(a->seed >> 32);
+            c.replica0 = (uint32_t)w0;
+            c.tab = build_tables(prep_beta(L, W, g, lnW));
+            c.per_lattice = 0;
+            c.tabs = nullptr;
+            if ((rc = run_sweeps(ctx, c, MC_INT8, spins + (int64_t)w0 * L * L, 0, a->prep_sweeps, nullptr, 0,
+                                 w + lay.prep, lay.prep_bytes, s)))
+                return rc;
+        }
+        if ((rc = device_check(ctx, launch_muca_settle(spins, E, L, W, s), "walker settle"))) return rc;
+    }
     std::vector<uint32_t> T;
     std::vector<int64_t> H((size_t)K + 1);
     uint64_t sweep = 0;
     int it = 0;
     bool converged = false;
     double ratio = 0.0;
+    int R = a->rec_sweeps;
+    const int Rmax = std::max(a->rec_max, a->rec_sweeps);
+    double prev = 0.0;
     while (it < a->max_iter) {
         muca_table(L, lnW.data(), T);
-        if ((rc = run_muca_sweeps(ctx, L, W, spins, E, T, a->seed, sweep, a->eq_sweeps, 0, nullptr, w, lay, s))) return rc;
-        sweep += (uint64_t)a->eq_sweeps;
+        const int neq = a->eq_sweeps + a->eq_scale * R;
+        if ((rc = run_muca_sweeps(ctx, L, W, spins, E, T, a->seed, sweep, neq, 0, nullptr, w, lay, s))) return rc;
+        sweep += (uint64_t)neq;
         if ((rc = device_check(ctx, launch_fill_i64(Hd, K + 1, 0, s), "histogram clear"))) return rc;
-        if ((rc = run_muca_sweeps(ctx, L, W, spins, E, T, a->seed, sweep, a->rec_sweeps, 1, Hd, w, lay, s))) return rc;
-        sweep += (uint64_t)a->rec_sweeps;
+        if ((rc = run_muca_sweeps(ctx, L, W, spins, E, T, a->seed, sweep, R, 1, Hd, w, lay, s))) return rc;
+        sweep += (uint64_t)R;
         if ((rc = copy_to_host(ctx, H.data(), Hd, H.size() * 8, s))) return rc;
         ++it;
         ratio = flatness(L, H);
@@ -197,6 +249,12 @@ int mc_muca_run(mc_ctx *ctx, const mc_muca_args *a, const double *lnW_init, int8
             converged = true;
             break;
         }
+        // longer iterations once the histogram reaches the whole window
+        bool covered = true;
+        for (int k = 0; k <= K; ++k)
+            if (k != 1 && H[(size_t)k] == 0) covered = false;
+        if (covered && (a->rec_rule == 0 || ratio <= prev)) R = std::min(2 * R, Rmax);
+        prev = covered ? ratio : 0.0;
         // W^(n+1) = W^(n) / H^(n) where H > 0, then ln W(E = 0) = 0
         for (int k = 0; k <= K; ++k)
             if (H[(size_t)k] > 0) lnW[(size_t)k] = lnW[(size_t)k] - std::log((double)H[(size_t)k]);

@@ -8,20 +8,46 @@
 namespace mcs {
 
 // Bytes of one packed copy of all lattices: one bit per spin.
-static size_t packed_bytes(const Geom &g) { return (size_t)g.count * (size_t)g.Ly * (size_t)(g.Lx / 8); }
+static size_t packed_bytes(const Geom &g)
+{
+    return (size_t)g.count * (size_t)g.Ly * (size_t)(g.dims == 3 ? g.Lz : 1) * (size_t)(g.Lx / 8);
+}
 
-// Two packed copies (ping-pong between the launches of one call).
+static bool fused2d_geom(const Geom &g, int layout)
+{
+    return layout == MC_INT8 && g.dims == 2 && g.Lx % 64 == 0 && g.Lx <= 16384;
+}
+
+static bool fused3d_geom(const Geom &g, int layout)
+{
+    return layout == MC_INT8 && g.dims == 3 && g.Lx % 64 == 0 && g.Lx <= 4096 && g.Ly >= 4 && g.Lz >= 4;
+}
+
+// Two packed copies (ping-pong between the launches of one call); in 3D also
+// the couplings in packed form (three directions), whether or not a call has
+// couplings.
 size_t fused_workspace_bytes(const Geom &g, int layout)
 {
-    if (layout == MC_INT8 && g.dims == 2 && g.Lx % 64 == 0 && g.Lx <= 16384) return 2 * packed_bytes(g);
+    if (fused2d_geom(g, layout)) return 2 * packed_bytes(g);
+    if (fused3d_geom(g, layout)) {
+        Geom one = g;
+        one.count = 1;
+        return 2 * packed_bytes(g) + 3 * packed_bytes(one);
+    }
     return 0;
 }
 
-// Default launch shape: enough bands to give every CU work, sweeps per launch
-// limited so the redone halo stays small.
+// Default launch shape of the 2D kernel: enough bands to give every CU work,
+// sweeps per launch limited so the redone halo stays small.
 TilePlan default_tile_plan(const Geom &g)
 {
     TilePlan p;
+    if (g.dims == 3) {
+        p.H = std::min(16, std::min(g.Ly, g.Lz));
+        p.K = 1;
+        p.threads = 256;
+        return p;
+    }
     const int want_tiles = 256;
     const int64_t per = std::max<int64_t>(1, (int64_t)want_tiles / std::max(1, g.count));
     int H = (int)std::max<int64_t>(4, g.Ly / per);
@@ -40,17 +66,27 @@ TilePlan default_tile_plan(const Geom &g)
 // A row of Wd = Lx/64 words is spread over the threads; when it is wider than
 // the workgroup every thread must take the same number of words, because the
 // tie queue's fill level is kept wave-uniform by all lanes taking part in the
-// same ballots.
+// same ballots.  3D tiles are H x H rows (y, z); their LDS (with room for
+// couplings) must fit in 96 KB.
 static bool plan_ok(const Geom &g, const TilePlan &p)
 {
     const int Wd = g.Lx / 64;
-    return p.H >= 1 && p.K >= 1 && p.K <= 8 && p.threads >= 64 && p.threads <= 1024 && p.threads % 64 == 0 &&
-           (Wd <= p.threads || Wd % p.threads == 0) && tile2d_lds_bytes(g.Lx, std::min(p.H, g.Ly), p.K) <= 65536;
+    if (p.H < 1 || p.K < 1 || p.threads < 64 || p.threads > 1024 || p.threads % 64 != 0) return false;
+    if (g.dims == 3)
+        return p.K <= 4 && Wd <= p.threads && p.H <= std::min(g.Ly, g.Lz) &&
+               tile3d_lds_bytes(g.Lx, p.H, p.K, true) <= 98304;
+    return p.K <= 8 && (Wd <= p.threads || Wd % p.threads == 0) &&
+           tile2d_lds_bytes(g.Lx, std::min(p.H, g.Ly), p.K) <= 65536;
+}
+
+static std::tuple<int, int, int, int, int> plan_key(const Geom &g)
+{
+    return std::make_tuple(g.dims, g.Lx, g.Ly, g.dims == 3 ? g.Lz : 1, g.count);
 }
 
 static TilePlan plan_for(mc_ctx *ctx, const Geom &g)
 {
-    auto it = ctx->tile_plans.find(std::make_tuple(g.Lx, g.Ly, g.count));
+    auto it = ctx->tile_plans.find(plan_key(g));
     if (it != ctx->tile_plans.end()) return it->second;
     return default_tile_plan(g);
 }
@@ -77,15 +113,24 @@ static int run_fused(mc_ctx *ctx, const SweepCall &c, const TilePlan &p, int8_t 
     if (EM) e = launch_fill_i64(EM, (int64_t)nsweeps * em_stride, 0, s);
     const std::vector<int> sizes = split_launches(nsweeps, p.K);
     char *pk[2] = {ws, ws + packed_bytes(c.g)};
+    const bool three = c.g.dims == 3;
+    uint32_t *Jp = nullptr;
+    if (three && c.J && e == hipSuccess) {
+        Jp = (uint32_t *)(ws + 2 * packed_bytes(c.g));
+        e = launch_pack_couplings(c.g, c.J, Jp, s);
+    }
     int done = 0;
-    const int H = std::min(p.H, c.g.Ly);
     const size_t m = sizes.size();
     for (size_t i = 0; i < m && e == hipSuccess; ++i) {
         const bool first = i == 0, last = i + 1 == m;
         const void *src = first ? (const void *)spins : (const void *)pk[(i - 1) & 1];
         void *dst = last ? (void *)spins : (void *)pk[i & 1];
-        e = launch_tile2d(c, src, first ? 0 : 1, dst, last ? 0 : 1, sweep0 + (uint64_t)done, sizes[i], H, p.threads,
-                          EM, em_stride, done, s);
+        if (three)
+            e = launch_tile3d(c, src, first ? 0 : 1, dst, last ? 0 : 1, Jp, sweep0 + (uint64_t)done, sizes[i], p.H,
+                              p.threads, EM, em_stride, done, s);
+        else
+            e = launch_tile2d(c, src, first ? 0 : 1, dst, last ? 0 : 1, sweep0 + (uint64_t)done, sizes[i],
+                              std::min(p.H, c.g.Ly), p.threads, EM, em_stride, done, s);
         done += sizes[i];
     }
     return device_check(ctx, e, "mc_sweep fused launch");
@@ -94,10 +139,20 @@ static int run_fused(mc_ctx *ctx, const SweepCall &c, const TilePlan &p, int8_t 
 int run_sweeps(mc_ctx *ctx, const SweepCall &c, int layout, void *spins, uint64_t sweep0, int nsweeps,
                int64_t *EM, int64_t em_stride, void *ws, size_t ws_bytes, hipStream_t s)
 {
-    if (tile2d_supported(c, layout) && ws && ws_bytes >= fused_workspace_bytes(c.g, layout)) {
+    const bool fused = (tile2d_supported(c, layout) || tile3d_supported(c, layout)) && ws &&
+                       ws_bytes >= fused_workspace_bytes(c.g, layout);
+    if (fused) {
         const TilePlan p = plan_for(ctx, c.g);
         if (plan_ok(c.g, p))
             return run_fused(ctx, c, p, (int8_t *)spins, (char *)ws, sweep0, nsweeps, EM, em_stride, s);
+    }
+    if (msc_fast_supported(c, layout)) {
+        hipError_t e = EM ? launch_fill_i64(EM, (int64_t)nsweeps * em_stride, 0, s) : hipSuccess;
+        for (int t = 0; t < nsweeps && e == hipSuccess; ++t)
+            for (int phase = 0; phase < 2 && e == hipSuccess; ++phase)
+                e = launch_msc_phase(c, (uint64_t *)spins, sweep0 + (uint64_t)t, phase, EM ? EM + t * em_stride : nullptr,
+                                     s);
+        return device_check(ctx, e, "mc_sweep multi-spin launch");
     }
     for (int t = 0; t < nsweeps; ++t) {
         const uint64_t sweep = sweep0 + (uint64_t)t;
@@ -130,7 +185,7 @@ int mc_set_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t H, int32_t K, int
     p.K = K;
     p.threads = threads;
     if (!plan_ok(g, p)) return fail(ctx, MC_E_RANGE, "tile plan H=%d K=%d threads=%d not usable", H, K, threads);
-    ctx->tile_plans[std::make_tuple(g.Lx, g.Ly, g.count)] = p;
+    ctx->tile_plans[plan_key(g)] = p;
     return MC_OK;
 }
 
@@ -149,41 +204,64 @@ int mc_get_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t *H, int32_t *K, i
 int mc_tune_sweep(mc_ctx *ctx, const mc_geom *geom, void *scratch_a, void *scratch_b, double beta, int32_t sweeps,
                   void *stream)
 {
+    return mc_tune_sweep_rule(ctx, geom, MC_METROPOLIS, scratch_a, scratch_b, beta, sweeps, stream);
+}
+
+int mc_tune_sweep_rule(mc_ctx *ctx, const mc_geom *geom, int32_t rule, void *scratch_a, void *scratch_b, double beta,
+                       int32_t sweeps, void *stream)
+{
     if (!ctx) return MC_E_INVAL;
     int rc = check_geom(ctx, geom, true);
     if (rc) return rc;
     if (!scratch_a || !scratch_b) return fail(ctx, MC_E_INVAL, "scratch buffers are NULL");
+    if (rule != MC_METROPOLIS && rule != MC_HEATBATH) return fail(ctx, MC_E_INVAL, "unknown rule %d", rule);
     if (!(beta >= 0.0) || sweeps < 1 || sweeps > 1000) return fail(ctx, MC_E_RANGE, "beta or sweeps out of range");
     const Geom g = to_geom(geom);
     SweepCall c;
     c.g = g;
     c.J = nullptr;
-    c.rule = MC_METROPOLIS;
+    c.rule = rule;
     c.seed_lo = 1;
     c.seed_hi = 0;
     c.replica0 = 0;
     c.tab = build_tables(beta);
     c.per_lattice = 0;
     c.tabs = nullptr;
-    if (!tile2d_supported(c, geom->layout)) return fail(ctx, MC_E_LAYOUT, "no tunable kernel for this geometry");
+    const bool three = g.dims == 3;
+    if (!(three ? tile3d_supported(c, geom->layout) : tile2d_supported(c, geom->layout)))
+        return fail(ctx, MC_E_LAYOUT, "no tunable kernel for this geometry and rule");
     if ((rc = set_device(ctx))) return rc;
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(ctx, MC_E_DEVICE, "hipEventCreate failed");
+    auto launch = [&](const void *src, int inp, void *dst, int outp, uint64_t sweep0, int K, const TilePlan &p,
+                      int64_t *em) {
+        return three ? launch_tile3d(c, src, inp, dst, outp, nullptr, sweep0, K, p.H, p.threads, em, 2 * g.count, 0, s)
+                     : launch_tile2d(c, src, inp, dst, outp, sweep0, K, std::min(p.H, g.Ly), p.threads, em,
+                                     2 * g.count, 0, s);
+    };
     // a hot lattice, packed into scratch_b
+    TilePlan conv = default_tile_plan(g);
     hipError_t e = launch_init_int8(g, (int8_t *)scratch_a, 1, 1, 0, s);
-    if (e == hipSuccess) e = launch_tile2d(c, scratch_a, 0, scratch_b, 1, 0, 0, std::min(16, g.Ly), 256, nullptr, 0, 0, s);
+    if (e == hipSuccess) e = launch(scratch_a, 0, scratch_b, 1, 0, 0, conv, nullptr);
     // per-sweep E, M of the timed launches: past the packed copy in scratch_a
     // (count N / 8 bytes of packed rows; count N / 2 >= that + 16 K count)
     int64_t *em = (int64_t *)((char *)scratch_a + (size_t)g.count * (size_t)g.N / 2);
     TilePlan best = default_tile_plan(g);
     float best_ms = 1e30f;
-    const int Hs[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128};
-    const int Ks[] = {1, 2, 3, 4, 6, 8};
-    const int Ts[] = {256, 512, 1024};
+    std::vector<int> Hs, Ks, Ts;
+    if (three) {
+        Hs = {4, 6, 8, 12, 16, 24, 32};
+        Ks = {1, 2, 3, 4};
+        Ts = {64, 128, 256, 512, 1024};
+    } else {
+        Hs = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128};
+        Ks = {1, 2, 3, 4, 6, 8};
+        Ts = {256, 512, 1024};
+    }
     for (int H : Hs) {
-        if (H > g.Ly) continue;
+        if (H > g.Ly || (three && H > g.Lz)) continue;
         for (int K : Ks)
             for (int T : Ts) {
                 TilePlan p;
@@ -197,13 +275,13 @@ int mc_tune_sweep(mc_ctx *ctx, const mc_geom *geom, void *scratch_a, void *scrat
                 // launches between the two scratch buffers, per-sweep E, M into
                 // the unused tail of scratch_a; a warm-up launch, then the best
                 // of two timed runs
-                e = launch_tile2d(c, scratch_b, 1, scratch_a, 1, 0, K, H, T, em, 2 * g.count, 0, s);
+                e = launch(scratch_b, 1, scratch_a, 1, 0, K, p, em);
                 float ms = 1e30f;
                 for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
                     hipEventRecord(e0, s);
                     for (int i = 0; i < n / K && e == hipSuccess; ++i)
-                        e = launch_tile2d(c, (i & 1) ? scratch_b : scratch_a, 1, (i & 1) ? scratch_a : scratch_b, 1,
-                                          (uint64_t)i * K, K, H, T, em, 2 * g.count, 0, s);
+                        e = launch((i & 1) ? scratch_b : scratch_a, 1, (i & 1) ? scratch_a : scratch_b, 1,
+                                   (uint64_t)i * K, K, p, em);
                     hipEventRecord(e1, s);
                     if (e == hipSuccess) e = hipEventSynchronize(e1);
                     float t = 0;
@@ -220,7 +298,7 @@ int mc_tune_sweep(mc_ctx *ctx, const mc_geom *geom, void *scratch_a, void *scrat
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (e != hipSuccess) return device_check(ctx, e, "mc_tune_sweep");
-    ctx->tile_plans[std::make_tuple(g.Lx, g.Ly, g.count)] = best;
+    ctx->tile_plans[plan_key(g)] = best;
     return MC_OK;
 }
 

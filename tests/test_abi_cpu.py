@@ -96,3 +96,34 @@ def test_other_argument_errors(ctx):
     assert mcs._lib.mc_measure(ctx, ctypes.byref(g), FAKE, None, None, None) == mcs.MC_E_INVAL
     assert mcs._lib.mc_couplings(ctx, ctypes.byref(g), None, 1, None) == mcs.MC_E_INVAL
     assert mcs._lib.mc_sweep(None, ctypes.byref(g), FAKE, None, None, None, None, 0, None) == mcs.MC_E_INVAL
+
+
+def test_mlp_training_set_matches_oracle(ctx):
+    # host-only call: features and targets from converged weights, bit-equal
+    # to the oracle's FP64 values rounded to FP32; level k = 1 left out
+    import numpy as np
+    from oracle import mlp
+
+    rng = np.random.default_rng(3)
+    lnW = {L: np.cumsum(rng.normal(0, 2, L * L // 2 + 1)) for L in (4, 6, 12)}
+    Ls = sorted(lnW)
+    cap = sum(L * L // 2 for L in Ls)
+    X = np.zeros((cap, 2), dtype=np.float32)
+    Y = np.zeros(cap, dtype=np.float32)
+    n = ctypes.c_int32()
+    Larr = (ctypes.c_int32 * 3)(*Ls)
+    parr = (ctypes.POINTER(ctypes.c_double) * 3)(*[lnW[L].ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for L in Ls])
+    fp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    assert mcs._lib.mc_mlp_training_set(ctx, 3, Larr, parr, fp(X), fp(Y), cap, ctypes.byref(n)) == 0
+    Xo, Yo = mlp.training_set(lnW)
+    assert n.value == cap == len(Yo)
+    assert np.array_equal(X, Xo.astype(np.float32)) and np.array_equal(Y, Yo.astype(np.float32))
+    # too small a buffer, a non-finite weight, an odd L
+    assert mcs._lib.mc_mlp_training_set(ctx, 3, Larr, parr, fp(X), fp(Y), cap - 1, ctypes.byref(n)) == mcs.MC_E_RANGE
+    lnW[6][5] = np.nan
+    assert mcs._lib.mc_mlp_training_set(ctx, 3, Larr, parr, fp(X), fp(Y), cap, ctypes.byref(n)) == mcs.MC_E_RANGE
+    lnW[6][5] = 0.0
+    lnW[6][1] = np.inf  # the empty level is ignored
+    assert mcs._lib.mc_mlp_training_set(ctx, 3, Larr, parr, fp(X), fp(Y), cap, ctypes.byref(n)) == 0
+    Larr[0] = 5
+    assert mcs._lib.mc_mlp_training_set(ctx, 3, Larr, parr, fp(X), fp(Y), cap, ctypes.byref(n)) == mcs.MC_E_SHAPE

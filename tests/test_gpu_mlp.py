@@ -76,3 +76,45 @@ def test_training_follows_fp64_adam(ctx, data):
     y = ctx.mlp_predict(pd, torch.from_numpy(X32).cuda()).cpu().numpy()
     y_ref, _ = mlp.forward(pd.cpu().numpy().astype(np.float64), X32.astype(np.float64))
     assert np.max(np.abs(y - y_ref)) <= 1e-5
+
+
+@pytest.mark.parametrize("L", [16, 64, 128])
+def test_lnw_init_vs_fp64(ctx, data, L):
+    # initial weights at a size outside the training set: -N y from the GPU
+    # forward pass against the FP64 forward pass of the same parameters
+    X, Y = data
+    pd = ctx.mlp_init(2)
+    ctx.mlp_train(pd, torch.from_numpy(X.astype(np.float32)).cuda(), torch.from_numpy(Y.astype(np.float32)).cuda(),
+                  100, lr=3e-3)
+    lnW, fb = ctx.mlp_lnw_init(pd, L)
+    assert not fb
+    ref = mlp.predict_lnW(pd.cpu().numpy().astype(np.float64), L)
+    N = L * L
+    assert lnW[-1] == 0.0
+    assert np.max(np.abs(lnW - ref)) <= 2e-5 * N
+
+
+def test_lnw_init_falls_back_to_flat(ctx):
+    p = ctx.mlp_init(2)
+    p[-1] = float("nan")  # b3: every prediction NaN
+    lnW, fb = ctx.mlp_lnw_init(p, 32)
+    assert fb and np.all(lnW == 0.0)
+
+
+def test_training_replays_continue_the_epoch_count(ctx, data):
+    # 1200 epochs run as two replays of a 500-epoch graph plus a 200-epoch
+    # graph: the first 300 losses equal a 300-epoch call bit for bit, and the
+    # curve keeps following the FP64 trajectory across the replay boundaries
+    X, Y = data
+    X32, Y32 = X.astype(np.float32), Y.astype(np.float32)
+    p0 = mlp.init_params(5)
+    Xd, Yd = torch.from_numpy(X32).cuda(), torch.from_numpy(Y32).cuda()
+    pa = torch.from_numpy(p0.astype(np.float32)).cuda()
+    pb = torch.from_numpy(p0.astype(np.float32)).cuda()
+    short = ctx.mlp_train(pa, Xd, Yd, 300, lr=3e-3).cpu().numpy()
+    long_ = ctx.mlp_train(pb, Xd, Yd, 1200, lr=3e-3).cpu().numpy()
+    assert np.array_equal(long_[:300], short)
+    _, log_ref = mlp.train(p0, X32.astype(np.float64), Y32.astype(np.float64), 700, lr=3e-3)
+    rel = np.abs(long_[:700].astype(np.float64) - log_ref) / log_ref
+    assert np.max(rel) <= 1e-2, np.max(rel)
+    assert np.all(np.isfinite(long_)) and long_[-1] < long_[500] < long_[0]

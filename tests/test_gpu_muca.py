@@ -40,10 +40,11 @@ def _weights(L, kind, seed=0):
 
 
 @pytest.mark.parametrize("L,W", [(8, 100), (16, 64), (24, 70), (48, 65)])
-def test_start_parity(ctx, L, W):
-    spins, E = ctx.muca_start(L, W, 19 + L)
+@pytest.mark.parametrize("start", [0, 1])
+def test_start_parity(ctx, L, W, start):
+    spins, E = ctx.muca_start(L, W, 19 + L, start=start)
     torch.cuda.synchronize()
-    os_, oE = oracle.muca_start(L, W, 19 + L)
+    os_, oE = oracle.muca_start(L, W, 19 + L, start)
     assert np.array_equal(spins.cpu().numpy().reshape(-1), os_)
     assert np.array_equal(E.cpu().numpy(), oE)
 
@@ -77,10 +78,29 @@ def _compare_runs(g, o):
     assert g["history"] == pytest.approx(o["history"], abs=0, rel=0)
 
 
-def test_run_parity_small(ctx):
-    args = dict(eq_sweeps=2, rec_sweeps=40, max_iter=30, prod_sweeps=200)
+@pytest.mark.parametrize("start,rec_max,eq_scale", [(0, 0, 0), (1, 0, 0), (1, 320, 0), (0, 160, 1)])
+def test_run_parity_small(ctx, start, rec_max, eq_scale):
+    args = dict(eq_sweeps=2, rec_sweeps=5 if rec_max else 40, max_iter=30, prod_sweeps=200, start=start,
+                rec_max=rec_max, eq_scale=eq_scale)
     g = ctx.muca_run(8, 1024, 27, **args)
     o = oracle.muca_run(8, 1024, 27, **args)
+    _compare_runs(g, o)
+
+
+@pytest.mark.parametrize("L,W,learned", [(8, 1000, False), (8, 1000, True), (12, 96, True)])
+def test_run_parity_prepared_walkers_stall_rule(ctx, L, W, learned):
+    # walkers thermalised to the initial weights (canonical sweeps, fused or
+    # generic kernel), iteration length doubled on stalled flatness; initial
+    # weights: flat, or a smooth approximation of -ln g
+    lnW0 = None
+    if learned:
+        K = L * L // 2
+        e = np.arange(K + 1) / K
+        lnW0 = -(L * L) * 0.69 * np.sin(0.5 * np.pi * e) + 3.0 * e
+    args = dict(eq_sweeps=2, rec_sweeps=5, max_iter=40, prod_sweeps=100, start=1, rec_max=160, prep_sweeps=6,
+                rec_rule=1, lnW_init=lnW0)
+    g = ctx.muca_run(L, W, 41, **args)
+    o = oracle.muca_run(L, W, 41, **args)
     _compare_runs(g, o)
 
 

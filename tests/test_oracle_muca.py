@@ -10,10 +10,13 @@ simulations", Eq. muca, Eq. weight_modification, count-again rule).
 * The plain recursion converges at small L and its ln g agrees with the exact
   density of states.
 * Acceptance table: ceil(min(1, W(E')/W(E)) 2^32).
+* Stratified walker starts: the integer disorder level equals its rounded
+  closed form, and the starting energies follow -2N (1 - c/128)^2.
 """
 import math
 
 import numpy as np
+import pytest
 
 import oracle
 from oracle import exact
@@ -104,3 +107,39 @@ def test_plain_recursion_converges_to_exact_lng():
     c = np.logaddexp.reduce(ex) - np.logaddexp.reduce(est)
     err = np.max(np.abs(est + c - ex))
     assert err < 0.03, err
+
+
+@pytest.mark.parametrize("W", [1, 7, 100, 4096])
+def test_stratified_level_is_rounded_closed_form(W):
+    # integer definition against 128 (1 - sqrt(1 - (w + 1/2)/W)) rounded
+    got = [oracle.muca_strat_level(w, W) for w in range(W)]
+    ref = [math.floor(128.0 * (1.0 - math.sqrt(1.0 - (w + 0.5) / W)) + 0.5) for w in range(W)]
+    assert got == ref
+    assert all(a <= b for a, b in zip(got, got[1:]))
+
+
+def test_stratified_start_spreads_energies():
+    # walker w flips each ground-state spin with probability c_w / 256, so its
+    # energy is -2N (1 - c_w/128)^2 on average (independent flips, nearest
+    # neighbours both flipped or not with probability p^2 + (1-p)^2)
+    L, W = 32, 64
+    N = L * L
+    spins, E = oracle.muca_start(L, W, 9, oracle.MUCA_STRATIFIED)
+    assert np.all(E <= 0)
+    c = np.array([oracle.muca_strat_level(w, W) for w in range(W)])
+    p = c / 256.0
+    expect = -2.0 * N * (1.0 - 2.0 * p) ** 2
+    sigma = np.sqrt(2.0 * N * 4.0 * (1.0 - (1.0 - 2.0 * p) ** 4) + 1.0)  # per-bond variance bound
+    z = (E - expect) / sigma
+    assert np.all(np.abs(z) < 6.0)
+    assert c[0] == 1 and oracle.muca_strat_level(0, 4096) == 0  # 4096 walkers: walker 0 is a ground state
+    # start 0 equals the hot start of each walker's replica id
+    hs, hE = oracle.muca_start(L, 5, 9, oracle.MUCA_HOT)
+    for w in range(5):
+        s = oracle.init(2, L, oracle.HOT, 9, w).reshape(-1)
+        e, m = oracle.measure(2, L, s)
+        if e > 0:
+            s = s.reshape(L, L).copy()
+            s[(np.add.outer(np.arange(L), np.arange(L)) % 2) == 1] *= -1
+            s = s.reshape(-1)
+        assert np.array_equal(hs[w * N:(w + 1) * N], s)
