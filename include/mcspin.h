@@ -250,6 +250,12 @@ int mc_muca_sweeps(mc_ctx *ctx, int32_t L, int32_t walkers, int8_t *spins, int64
                    uint64_t seed, uint64_t sweep0, int32_t nsweeps, int32_t record, int64_t *H, void *ws,
                    size_t ws_bytes, void *stream);
 
+/* Progress of a long multicanonical run, called on the calling thread after
+ * every weight iteration (iteration >= 1, its flatness, sweeps per walker so
+ * far) and after every 1000 production sweeps (iteration 0, flatness -1,
+ * production sweeps so far).  It must not call back into the library.      */
+typedef void (*mc_progress_fn)(void *user, int32_t iteration, double flatness, int64_t sweeps);
+
 typedef struct {
     int32_t L, walkers;
     int32_t eq_sweeps;    /* unrecorded sweeps at the start of each iteration   */
@@ -275,6 +281,8 @@ typedef struct {
                              iteration that reached every window level; 1:
                              only when such an iteration's flatness did not
                              improve on the previous iteration's             */
+    mc_progress_fn progress;  /* or NULL                                       */
+    void *progress_user;
 } mc_muca_args;
 
 typedef struct {
@@ -341,8 +349,11 @@ int mc_mlp_predict(mc_ctx *ctx, const float *params, const float *X, int32_t n, 
  * simulations": the weights the recursion of Eq. weight_modification
  * produced at smaller L): for each lattice size Ls[i] (even, >= 4) and every
  * level k = 0 .. N/2 of the window E = 4k - 2N in [-2N, 0] except the empty
- * level k = 1, one sample x = (E/N + 1, 32/L - 1), y = -(lnW[k] - lnW[N/2]) / N,
- * computed in FP64 and rounded to FP32.  lnW: host array of nL pointers to
+ * level k = 1, one sample x = (E/N + 1, 32/L - 1), y = -(lnW[k] - lnW[N/2]) / N
+ * - b(k), b(k) = h(k / 2N) - h(1/4) with h(x) = -x ln x - (1 - x) ln(1 - x)
+ * the entropy of independent flipped spins (it carries the ground-state
+ * singularity of g(E), so the network fits a smooth remainder), computed in
+ * FP64 and rounded to FP32.  lnW: host array of nL pointers to
  * N/2 + 1 doubles each (finite except at k = 1).  X: host float [cap][2],
  * Y: host float [cap]; *n_out = samples written.  MC_E_RANGE if they do not
  * fit in cap or a weight is not finite.  Host-only call.                   */
@@ -351,7 +362,7 @@ int mc_mlp_training_set(mc_ctx *ctx, int32_t nL, const int32_t *Ls, const double
 
 /* Initial log-weights of an L x L lattice from a trained network: the inputs
  * of every window level are formed on the device, the network runs as in
- * mc_mlp_predict, and lnW_out[k] = -N y(k) (FP64, host array of N/2 + 1),
+ * mc_mlp_predict, and lnW_out[k] = -N (y(k) + b(k)) (FP64, host array of N/2 + 1),
  * shifted so that lnW_out[N/2] = 0.  If any prediction is not finite the
  * plain method's flat start is returned instead (all zeros) and
  * *used_fallback = 1, else 0.  ws: device scratch of

@@ -8,7 +8,9 @@ Optimiser: Adam (bias-corrected moments).  Initialisation: Xavier-uniform
 weights w = (2u - 1) sqrt(6 / (fan_in + fan_out)), u = (r >> 8) 2^-24 with r
 the Philox word of parameter index idx (tag MLP_INIT, counter idx / 4, word
 idx mod 4), biases zero.  Inputs are (E/N + 1, 32/L - 1); the target is the
-entropy deficit y = -ln W(E) / N with ln W(0) = 0.
+entropy deficit -ln W(E) / N with ln W(0) = 0, less an analytic baseline (the
+entropy of independent flipped spins) that carries its ground-state
+singularity.
 
 The backward pass is the chain rule written out; the tests pin it against
 central finite differences of the loss.
@@ -104,27 +106,47 @@ def train(p, X, Y, epochs, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     return p, np.array(losses)
 
 
+def _gas_entropy(x):
+    """Entropy per site of independent flipped spins at density x: -x ln x -
+    (1 - x) ln(1 - x), 0 at x = 0 (libm log and log1p, as the library)."""
+    return 0.0 if x <= 0.0 else -x * math.log(x) - (1.0 - x) * math.log1p(-x)
+
+
+def baseline(L):
+    """Output baseline b(k) = h(k / 2N) - h(1/4), h the entropy of a gas of
+    independent flipped spins (the low-energy behaviour of g(E), where a site
+    in the window's lower end has an isolated flipped spin per 8 of energy),
+    so that the network fits the smooth remainder instead of the x ln x
+    singularity at the ground state."""
+    N = L * L
+    K = N // 2
+    b = np.array([_gas_entropy(k / (2.0 * N)) for k in range(K + 1)])
+    return b - b[K]
+
+
 def training_set(lnW_by_L):
     """(X, Y) from converged ln W per L: every window level but k = 1, with
-    ln W taken relative to its value at E = 0 (level N/2)."""
+    ln W taken relative to its value at E = 0 (level N/2), minus the
+    baseline: y = -(ln W - ln W(0)) / N - b."""
     X, Y = [], []
     for L, lnW in sorted(lnW_by_L.items()):
         N = L * L
         K = N // 2
         lnW = np.asarray(lnW, dtype=np.float64)
+        b = baseline(L)
         k = np.array([i for i in range(K + 1) if i != 1])
         E = 4 * k - 2 * N
         X.append(features(E, N, L))
-        Y.append(-(lnW[k] - lnW[K]) / N)
+        Y.append(-(lnW[k] - lnW[K]) / N - b[k])
     return np.concatenate(X), np.concatenate(Y)
 
 
 def predict_lnW(p, L):
-    """Initial ln W(E) = -N * y(E/N, 1/L) over the window levels, shifted to
-    ln W(0) = 0."""
+    """Initial ln W(E) = -N (y(E/N, 1/L) + b) over the window levels, shifted
+    to ln W(0) = 0."""
     N = L * L
     K = N // 2
     E = 4 * np.arange(K + 1) - 2 * N
     y, _ = forward(p, features(E, N, L))
-    lnW = -N * y
+    lnW = -N * (y + baseline(L))
     return lnW - lnW[K]

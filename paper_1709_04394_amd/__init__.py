@@ -58,12 +58,15 @@ class PAArgs(ctypes.Structure):
                 ("nsteps", ctypes.c_int32), ("beta", ctypes.POINTER(ctypes.c_double))]
 
 
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_int64)
+
+
 class MucaArgs(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("walkers", ctypes.c_int32), ("eq_sweeps", ctypes.c_int32),
                 ("rec_sweeps", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("prod_sweeps", ctypes.c_int32),
                 ("flat", ctypes.c_double), ("seed", ctypes.c_uint64), ("start", ctypes.c_int32),
                 ("rec_max", ctypes.c_int32), ("eq_scale", ctypes.c_int32), ("prep_sweeps", ctypes.c_int32),
-                ("rec_rule", ctypes.c_int32)]
+                ("rec_rule", ctypes.c_int32), ("progress", PROGRESS_FN), ("progress_user", ctypes.c_void_p)]
 
 
 class MucaStats(ctypes.Structure):
@@ -388,15 +391,16 @@ class Context:
                     "mc_muca_sweeps")
 
     def muca_run(self, L, walkers, seed, eq_sweeps, rec_sweeps, max_iter, prod_sweeps, flat=0.8, lnW_init=None,
-                 spins=None, ws=None, start=0, rec_max=0, eq_scale=0, prep_sweeps=0, rec_rule=0):
+                 spins=None, ws=None, start=0, rec_max=0, eq_scale=0, prep_sweeps=0, rec_rule=0, progress=None):
         """Full multicanonical run; returns a dict like oracle.muca_run."""
         import numpy as np
 
         K1 = L * L // 2 + 1
         spins = torch.empty((walkers, L * L), dtype=torch.int8, device=self.device) if spins is None else spins
         ws = self.muca_workspace(L, walkers) if ws is None else ws
+        cb = PROGRESS_FN(progress) if progress is not None else PROGRESS_FN()
         a = MucaArgs(L, walkers, eq_sweeps, rec_sweeps, max_iter, prod_sweeps, float(flat), seed, start, rec_max,
-                     eq_scale, prep_sweeps, rec_rule)
+                     eq_scale, prep_sweeps, rec_rule, cb, None)
         init = None
         if lnW_init is not None:
             init = np.ascontiguousarray(lnW_init, dtype=np.float64)

@@ -12,6 +12,14 @@ namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Entropy per site of independent flipped spins at density x, 0 at x = 0.
+double gas_entropy(double x) { return x <= 0.0 ? 0.0 : -x * std::log(x) - (1.0 - x) * std::log1p(-x); }
+
+// Output baseline of level k of an N-site lattice: h(k / 2N) - h(1/4); the
+// network fits the entropy deficit minus this (the ground-state singularity
+// of g(E) is the flipped-spin gas's x ln x).
+double baseline(int k, int N) { return gas_entropy((double)k / (2.0 * N)) - gas_entropy(0.25); }
+
 struct MlpLayout {
     size_t part = 0, m = 0, v = 0, step = 0, loss = 0, total = 0;
 };
@@ -143,7 +151,7 @@ int mc_mlp_training_set(mc_ctx *ctx, int32_t nL, const int32_t *Ls, const double
             const double E = 4.0 * k - 2.0 * N;
             X[2 * j] = (float)(E / (double)N + 1.0);
             X[2 * j + 1] = (float)(32.0 / (double)L - 1.0);
-            Y[j] = (float)(-(lnW[i][k] - ref) / (double)N);
+            Y[j] = (float)(-(lnW[i][k] - ref) / (double)N - baseline(k, N));
             ++j;
         }
     }
@@ -180,8 +188,9 @@ int mc_mlp_lnw_init(mc_ctx *ctx, const float *params, int32_t L, double *lnW_out
     bool finite = true;
     for (int k = 0; k <= K; ++k) finite = finite && std::isfinite(y[(size_t)k]);
     *used_fallback = finite ? 0 : 1;
-    const double ref = finite ? -(double)N * (double)y[(size_t)K] : 0.0;
-    for (int k = 0; k <= K; ++k) lnW_out[k] = finite ? -(double)N * (double)y[(size_t)k] - ref : 0.0;
+    const double ref = finite ? -(double)N * ((double)y[(size_t)K] + baseline(K, N)) : 0.0;
+    for (int k = 0; k <= K; ++k)
+        lnW_out[k] = finite ? -(double)N * ((double)y[(size_t)k] + baseline(k, N)) - ref : 0.0;
     return MC_OK;
 }
 

@@ -245,6 +245,7 @@ int mc_muca_run(mc_ctx *ctx, const mc_muca_args *a, const double *lnW_init, int8
         ++it;
         ratio = flatness(L, H);
         if (flat_out) flat_out[it - 1] = ratio;
+        if (a->progress) a->progress(a->progress_user, it, ratio, (int64_t)sweep);
         if (ratio >= a->flat) {
             converged = true;
             break;
@@ -269,7 +270,15 @@ int mc_muca_run(mc_ctx *ctx, const mc_muca_args *a, const double *lnW_init, int8
     if (a->prod_sweeps > 0) {
         muca_table(L, lnW.data(), T);
         if ((rc = device_check(ctx, launch_fill_i64(Hd, K + 1, 0, s), "histogram clear"))) return rc;
-        if ((rc = run_muca_sweeps(ctx, L, W, spins, E, T, a->seed, sweep, a->prod_sweeps, 1, Hd, w, lay, s))) return rc;
+        // in chunks, so that a progress callback hears from long runs
+        const int chunk = 1000;
+        for (int done = 0; done < a->prod_sweeps;) {
+            const int n = std::min(chunk, a->prod_sweeps - done);
+            if ((rc = run_muca_sweeps(ctx, L, W, spins, E, T, a->seed, sweep + (uint64_t)done, n, 1, Hd, w, lay, s)))
+                return rc;
+            done += n;
+            if (a->progress) a->progress(a->progress_user, 0, -1.0, (int64_t)done);
+        }
         if ((rc = copy_to_host(ctx, H.data(), Hd, H.size() * 8, s))) return rc;
     }
     for (int k = 0; k <= K; ++k) {

@@ -146,6 +146,9 @@ int run_sweeps(mc_ctx *ctx, const SweepCall &c, int layout, void *spins, uint64_
         if (plan_ok(c.g, p))
             return run_fused(ctx, c, p, (int8_t *)spins, (char *)ws, sweep0, nsweeps, EM, em_stride, s);
     }
+    if (small_supported(c, layout))
+        return device_check(ctx, launch_small(c, (int8_t *)spins, sweep0, nsweeps, EM, em_stride, s),
+                            "mc_sweep small-lattice launch");
     if (msc_fast_supported(c, layout)) {
         hipError_t e = EM ? launch_fill_i64(EM, (int64_t)nsweeps * em_stride, 0, s) : hipSuccess;
         for (int t = 0; t < nsweeps && e == hipSuccess; ++t)

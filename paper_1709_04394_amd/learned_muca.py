@@ -13,6 +13,7 @@ This module only sequences library calls; every step runs in libmcspin.
 """
 from __future__ import annotations
 
+import sys
 import time
 
 import numpy as np
@@ -42,8 +43,20 @@ def run_arm(ctx, L, seed, lnW_init=None, walkers=WALKERS, eq_sweeps=2, rec_sweep
     rec_max = REC_MAX.get(L, 10) if rec_max is None else rec_max
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    last = [t0]
+
+    def progress(_user, it, flatness, sweeps):
+        # a line at most every 20 s of a long run, on stderr
+        now = time.perf_counter()
+        if now - last[0] >= 20.0:
+            last[0] = now
+            phase = "iteration %d, flatness %.3f" % (it, flatness) if it > 0 else "production"
+            print("multicanonical L=%d: %s, %d sweeps per walker, %.0f s" % (L, phase, sweeps, now - t0),
+                  file=sys.stderr, flush=True)
+
     r = ctx.muca_run(L, walkers, seed, eq_sweeps, rec_sweeps, max_iter, prod_sweeps, flat=flat, lnW_init=lnW_init,
-                     start=start, rec_max=rec_max, eq_scale=eq_scale, prep_sweeps=prep_sweeps, rec_rule=rec_rule)
+                     start=start, rec_max=rec_max, eq_scale=eq_scale, prep_sweeps=prep_sweeps, rec_rule=rec_rule,
+                     progress=progress)
     r["seconds"] = time.perf_counter() - t0
     r["total_sweeps"] = int(r["sweeps_per_walker"]) * walkers
     r["prep_sweeps_per_walker"] = prep_sweeps

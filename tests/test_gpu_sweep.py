@@ -113,6 +113,21 @@ def test_3d(ctx, shape, rule, beta):
     _run_both(ctx, 3, shape, rule, beta, 11, 6, start=0)
 
 
+@pytest.mark.parametrize("dims,shape,rule,J", [(2, (516, 310), 0, False), (3, (34, 38, 124), 1, True)])
+def test_generic_kernels_large_odd_shapes(ctx, dims, shape, rule, J):
+    # too large for one workgroup's LDS and not a multiple of 64 wide: the
+    # generic half-sweep kernels
+    Jh = oracle.couplings(dims, shape, 3) if J else None
+    _run_both(ctx, dims, shape, rule, 0.3, 17, 4, J=Jh)
+
+
+def test_config_edwards_anderson_32(ctx):
+    # 3D +-J spin glass at L = 32, couplings and spins from seed 13, Metropolis
+    # at beta = 1 (the small-lattice kernel: whole lattice in one workgroup)
+    J = oracle.couplings(3, 32, 13)
+    _run_both(ctx, 3, (32, 32, 32), mcs.METROPOLIS, 1.0, 13, 200, J=J)
+
+
 def test_edwards_anderson(ctx):
     J = oracle.couplings(3, 8, 13)
     _run_both(ctx, 3, (8, 8, 8), mcs.METROPOLIS, 1.0, 13, 25, J=J)
