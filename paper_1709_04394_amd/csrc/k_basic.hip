@@ -148,12 +148,26 @@ __device__ __forceinline__ int neighbours(const Geom &g, Coord q, int64_t *nb, i
     return 4;
 }
 
-__device__ __forceinline__ bool lazy_below(uint32_t byte, const Thr &t, uint32_t k0, uint32_t k1, uint32_t j,
-                                           uint32_t replica, uint32_t sweep_lo, uint32_t w3lo)
+__device__ __forceinline__ bool lazy_below(uint32_t byte, uint32_t top, uint32_t low, uint32_t k0, uint32_t k1,
+                                           uint32_t j, uint32_t replica, uint32_t sweep_lo, uint32_t w3lo)
 {
-    if (byte != t.top) return byte < t.top;
+    if (byte != top) return byte < top;
     const uint4 lo = philox(make_uint4(j, replica, sweep_lo, w3lo), k0, k1);
-    return (lo.x & 0xFFFFFFu) < t.low;
+    return (lo.x & 0xFFFFFFu) < low;
+}
+
+// The call's thresholds copied to LDS (entries 0..3 Metropolis by dE / 4,
+// 4..16 heat-bath by h + 6): indexing the argument block by a per-lane value
+// would be a memory load per site.  Every thread of the block must call this
+// (it ends with a barrier).
+__device__ __forceinline__ void stage_tables(const SweepTables &t, uint32_t *top, uint32_t *low)
+{
+    if (threadIdx.x < 17) {
+        const Thr v = threadIdx.x < 4 ? t.met[threadIdx.x] : t.hb[threadIdx.x - 4];
+        top[threadIdx.x] = v.top;
+        low[threadIdx.x] = v.low;
+    }
+    __syncthreads();
 }
 
 // ----------------------------------------------------------------------------
@@ -165,6 +179,8 @@ __global__ void k_phase_int8(SweepCall c, int8_t *spins, uint32_t sweep_lo, uint
     const int64_t half = g.N >> 1;
     const int64_t t16 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t j0 = t16 * 16;
+    __shared__ uint32_t ttop[17], tlow[17];
+    stage_tables(c.tab, ttop, tlow);
     if (j0 >= half) return;
     int8_t *s = spins + (int64_t)l * g.N;
     const uint32_t rep = c.replica0 + (uint32_t)l;
@@ -184,10 +200,10 @@ __global__ void k_phase_int8(SweepCall c, int8_t *spins, uint32_t sweep_lo, uint
         if (c.rule == 0) {
             const int dE = 2 * si * h;
             bool acc = dE <= 0;
-            if (!acc) acc = lazy_below(byte, c.tab.met[dE >> 2], c.seed_lo, c.seed_hi, (uint32_t)j, rep, sweep_lo, w3lo);
+            if (!acc) acc = lazy_below(byte, ttop[dE >> 2], tlow[dE >> 2], c.seed_lo, c.seed_hi, (uint32_t)j, rep, sweep_lo, w3lo);
             out = acc ? (int8_t)-si : (int8_t)si;
         } else {
-            const bool up = lazy_below(byte, c.tab.hb[h + 6], c.seed_lo, c.seed_hi, (uint32_t)j, rep, sweep_lo, w3lo);
+            const bool up = lazy_below(byte, ttop[h + 10], tlow[h + 10], c.seed_lo, c.seed_hi, (uint32_t)j, rep, sweep_lo, w3lo);
             out = up ? (int8_t)1 : (int8_t)-1;
         }
         s[i] = out;
@@ -226,6 +242,8 @@ __global__ void k_phase_msc64(SweepCall c, uint64_t *words, uint32_t sweep_lo, u
     const int64_t half = g.N >> 1;
     const int64_t t16 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t j0 = t16 * 16;
+    __shared__ uint32_t ttop[17], tlow[17];
+    stage_tables(c.tab, ttop, tlow);
     if (j0 >= half) return;
     uint64_t *w = words + (int64_t)l * g.N;
     const int z = 2 * g.dims;
@@ -262,11 +280,11 @@ __global__ void k_phase_msc64(SweepCall c, uint64_t *words, uint32_t sweep_lo, u
             bool flip;
             if (c.rule == 0) {
                 const int dE = 2 * (z - 2 * a);
-                flip = dE <= 0 || lazy_below(byte, c.tab.met[dE >> 2], c.seed_lo, c.seed_hi, j, rep, sweep_lo, w3lo);
+                flip = dE <= 0 || lazy_below(byte, ttop[dE > 0 ? dE >> 2 : 0], tlow[dE > 0 ? dE >> 2 : 0], c.seed_lo, c.seed_hi, j, rep, sweep_lo, w3lo);
             } else {
                 const int si = ((S[k] >> b) & 1) ? -1 : 1;
                 const int h = si * (z - 2 * a);
-                const bool up = lazy_below(byte, c.tab.hb[h + 6], c.seed_lo, c.seed_hi, j, rep, sweep_lo, w3lo);
+                const bool up = lazy_below(byte, ttop[h + 10], tlow[h + 10], c.seed_lo, c.seed_hi, j, rep, sweep_lo, w3lo);
                 flip = up != (si > 0);
             }
             F[k] |= (uint64_t)flip << b;

@@ -53,7 +53,8 @@ def test_start_parity(ctx, L, W, start):
                                                (12, 64, "random", 1, 3), (16, 130, "flat", 2, 3),
                                                (24, 64, "random", 1, 2), (32, 65, "canonical", 1, 2),
                                                (48, 64, "random", 1, 1), (64, 64, "flat", 0, 1),
-                                               (96, 64, "random", 0, 1), (128, 64, "canonical", 0, 1)])
+                                               (96, 64, "random", 0, 1), (128, 64, "canonical", 0, 1),
+                                               (32, 130, "random", 2, 3), (64, 70, "canonical", 1, 2)])
 def test_sweeps_parity(ctx, L, W, kind, neq, nrec):
     seed = 5 + L
     lnW = _weights(L, kind, seed)
