@@ -157,8 +157,10 @@ def row_measurements(torch, mcs, ctx, dev):
     H = torch.zeros(Lm * Lm // 2 + 1, dtype=torch.int64, device=dev)
     lnW = np.zeros(Lm * Lm // 2 + 1)
     ctx.muca_sweeps(Lm, spins, E, lnW, 147, 0, 1, 1, H, wsm)
+    torch.cuda.synchronize()
     t0 = _t.perf_counter()
     ctx.muca_sweeps(Lm, spins, E, lnW, 147, 1, 4, 1, H, wsm)
+    torch.cuda.synchronize()
     el = _t.perf_counter() - t0
     rows["muca_4096_walkers_L128"] = {"value": Wm * Lm * Lm * 4 / (el * 1e9), "unit": "single-site updates/ns",
                                       "ms_per_sweep": el * 250.0}

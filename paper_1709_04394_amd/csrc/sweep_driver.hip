@@ -43,9 +43,14 @@ TilePlan default_tile_plan(const Geom &g)
 {
     TilePlan p;
     if (g.dims == 3) {
+        // 16 x 16 tiles give a 256^3 lattice one tile per CU; two sweeps per
+        // launch, 1024 threads (the tuner's choice there), reduced until the
+        // tile fits LDS with room for couplings
         p.H = std::min(16, std::min(g.Ly, g.Lz));
-        p.K = 1;
-        p.threads = 256;
+        p.K = 2;
+        p.threads = 1024;
+        while (p.K > 1 && tile3d_lds_bytes(g.Lx, p.H, p.K, true) > 98304) --p.K;
+        while (p.H > 1 && tile3d_lds_bytes(g.Lx, p.H, p.K, true) > 98304) p.H /= 2;
         return p;
     }
     const int want_tiles = 256;
