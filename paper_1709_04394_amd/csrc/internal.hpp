@@ -66,6 +66,12 @@ hipError_t launch_tile3d(const SweepCall &c, const void *src, int in_packed, voi
                          int64_t em_stride, int64_t em_sweep0, hipStream_t s);
 hipError_t launch_pack_couplings(const Geom &g, const int8_t *J, uint32_t *Jp, hipStream_t s);
 
+// int8 lattices with 32-site rows, bit-packed whole in one workgroup's LDS
+// (k_small_bits.hip)
+bool small_bits_supported(const SweepCall &c, int layout);
+hipError_t launch_small_bits(const SweepCall &c, int8_t *spins, uint64_t sweep0, int nsweeps, int64_t *EM,
+                             int64_t em_stride, hipStream_t s);
+
 // small int8 lattices held whole in one workgroup's LDS (k_small.hip)
 bool small_supported(const SweepCall &c, int layout);
 hipError_t launch_small(const SweepCall &c, int8_t *spins, uint64_t sweep0, int nsweeps, int64_t *EM,

@@ -151,6 +151,9 @@ int run_sweeps(mc_ctx *ctx, const SweepCall &c, int layout, void *spins, uint64_
         if (plan_ok(c.g, p))
             return run_fused(ctx, c, p, (int8_t *)spins, (char *)ws, sweep0, nsweeps, EM, em_stride, s);
     }
+    if (small_bits_supported(c, layout))
+        return device_check(ctx, launch_small_bits(c, (int8_t *)spins, sweep0, nsweeps, EM, em_stride, s),
+                            "mc_sweep small bit-packed lattice launch");
     if (small_supported(c, layout))
         return device_check(ctx, launch_small(c, (int8_t *)spins, sweep0, nsweeps, EM, em_stride, s),
                             "mc_sweep small-lattice launch");
