@@ -40,23 +40,52 @@ struct MscArgs {
     int64_t *EM;  // this sweep's [count * 64][2], or nullptr
 };
 
+// Lane exchange at xor distance D: ds_swizzle in its xor mode (and mask 0x1F,
+// xor mask D; within groups of 32 lanes) for D <= 16, a permute across the
+// wave for D = 32.
+template <int D>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t x)
+{
+    if constexpr (D == 32)
+        return (uint32_t)__shfl_xor((int)x, 32, 64);
+    else
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, (D << 10) | 0x1F);
+}
+
+// One stage of the transpose: lanes i and i ^ D swap d-bit blocks.  The lane
+// with bit D clear keeps the low block of each 2D-bit group and takes its
+// partner's low block into the high position; the other lane keeps the high
+// block and takes its partner's high block into the low position.  The select
+// is a per-lane mask, not a branch (the two lanes of a pair take different
+// sides).
+template <int D>
+__device__ __forceinline__ uint64_t transpose_stage(uint64_t v, int lane)
+{
+    constexpr uint64_t M = D == 32 ? 0x00000000FFFFFFFFull
+                         : D == 16 ? 0x0000FFFF0000FFFFull
+                         : D == 8  ? 0x00FF00FF00FF00FFull
+                         : D == 4  ? 0x0F0F0F0F0F0F0F0Full
+                         : D == 2  ? 0x3333333333333333ull
+                                   : 0x5555555555555555ull;
+    const uint32_t lo = xor_lane<D>((uint32_t)v), hi = xor_lane<D>((uint32_t)(v >> 32));
+    const uint64_t p = ((uint64_t)hi << 32) | lo;
+    const uint64_t sel = (lane & D) ? ~0ull : 0ull;
+    const uint64_t keep = M ^ sel;                      // M on the low side, ~M on the high side
+    const uint64_t up = p << D, down = p >> D;
+    const uint64_t t = up ^ ((up ^ down) & sel);        // partner's block moved into place
+    return (v & keep) | (t & ~keep);
+}
+
 // 64 x 64 bit transpose across the wave: on entry lane b holds row b, on exit
 // lane s holds column s (bit b of the result = bit s of lane b's row).
 __device__ __forceinline__ uint64_t transpose64(uint64_t v, int lane)
 {
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) {
-        const uint64_t m = d == 32 ? 0x00000000FFFFFFFFull
-                         : d == 16 ? 0x0000FFFF0000FFFFull
-                         : d == 8  ? 0x00FF00FF00FF00FFull
-                         : d == 4  ? 0x0F0F0F0F0F0F0F0Full
-                         : d == 2  ? 0x3333333333333333ull
-                                   : 0x5555555555555555ull;
-        const uint32_t lo = __shfl_xor((int)(uint32_t)v, d, 64), hi = __shfl_xor((int)(uint32_t)(v >> 32), d, 64);
-        const uint64_t p = ((uint64_t)hi << 32) | lo;
-        v = (lane & d) ? ((v & ~m) | ((p >> d) & m)) : ((v & m) | ((p & m) << d));
-    }
-    return v;
+    v = transpose_stage<32>(v, lane);
+    v = transpose_stage<16>(v, lane);
+    v = transpose_stage<8>(v, lane);
+    v = transpose_stage<4>(v, lane);
+    v = transpose_stage<2>(v, lane);
+    return transpose_stage<1>(v, lane);
 }
 
 template <int DIMS, bool MEASURE, bool HB, bool HASJ>

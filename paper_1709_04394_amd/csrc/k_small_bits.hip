@@ -88,6 +88,25 @@ __device__ __forceinline__ void unpack_row32(int8_t *p, uint32_t ev, uint32_t od
     }
 }
 
+// Row r = y + Ly z: the parity of (y + z) and the indices of its four (2D:
+// two) neighbouring rows.
+struct RowGeo {
+    int yz;  // (y + z) & 1
+    int ryp, rym, rzp, rzm;
+};
+
+__device__ __forceinline__ RowGeo row_geo(int r, int Ly, int Lz)
+{
+    const int y = r % Ly, z = r / Ly;
+    RowGeo g;
+    g.yz = (y + z) & 1;
+    g.ryp = y + 1 == Ly ? r - y : r + 1;
+    g.rym = y == 0 ? r + Ly - 1 : r - 1;
+    g.rzp = z + 1 == Lz ? r - (Lz - 1) * Ly : r + Ly;
+    g.rzm = z == 0 ? r + (Lz - 1) * Ly : r - Ly;
+    return g;
+}
+
 template <int DIMS, bool HB, bool HASJ>
 __global__ __launch_bounds__(1024) void k_small_bits(SmallBitsArgs a)
 {
@@ -118,35 +137,38 @@ __global__ __launch_bounds__(1024) void k_small_bits(SmallBitsArgs a)
     }
     __syncthreads();
     const uint32_t rep = a.replica0 + (uint32_t)l;
+    // geometry of this thread's first row (the only one when R <= threads)
+    const RowGeo g0 = row_geo(tid < R ? tid : 0, Ly, Lz);
     for (int t = 0; t < a.nsweeps; ++t) {
         const uint64_t sweep = a.sweep0 + (uint64_t)t;
         for (int c = 0; c < 2; ++c) {
             const uint32_t w3 = ctr_w3(kTagSweep, (uint32_t)c, sweep), w3lo = ctr_w3(kTagSweepLo, (uint32_t)c, sweep);
             for (int r = tid; r < R; r += nt) {
-                const int y = r % Ly, z = r / Ly;
-                const int p = (c + y + z) & 1;
-                const int ryp = y + 1 == Ly ? r - y : r + 1, rym = y == 0 ? r + Ly - 1 : r - 1;
-                const uint32_t s = S[p * R + r], o = S[(1 - p) * R + r];
+                const RowGeo rg = r == tid ? g0 : row_geo(r, Ly, Lz);
+                const int p = (c + rg.yz) & 1;
+                const int op = p ? R : 0, oq = p ? 0 : R;  // word offsets of parity p and 1 - p
+                const uint32_t s = S[op + r], o = S[oq + r];
+                // x neighbours: the other parity word shifted by one, selected
+                // without branching (neighbouring rows of a wave differ in p)
+                const uint32_t ol = rotl16(o), orr = rotr16(o);
                 uint32_t nb[6], jb[6];
-                nb[0] = p == 0 ? rotl16(o) : o;  // x - 1
-                nb[1] = p == 0 ? o : rotr16(o);  // x + 1
-                nb[2] = S[p * R + ryp];
-                nb[3] = S[p * R + rym];
+                nb[0] = p ? o : ol;   // x - 1
+                nb[1] = p ? orr : o;  // x + 1
+                nb[2] = S[op + rg.ryp];
+                nb[3] = S[op + rg.rym];
                 if (HASJ) {
-                    const uint32_t j0o = Jb[(1 - p) * R + r];
-                    jb[0] = p == 0 ? rotl16(j0o) : j0o;  // bond to x - 1: J_x of site x - 1
-                    jb[1] = Jb[p * R + r];               // bond to x + 1: J_x of this site
-                    jb[2] = Jb[(2 + p) * R + r];
-                    jb[3] = Jb[(2 + p) * R + rym];
+                    const uint32_t j0o = Jb[oq + r];
+                    jb[0] = p ? j0o : rotl16(j0o);  // bond to x - 1: J_x of site x - 1
+                    jb[1] = Jb[op + r];             // bond to x + 1: J_x of this site
+                    jb[2] = Jb[2 * R + op + r];
+                    jb[3] = Jb[2 * R + op + rg.rym];
                 }
                 if (DIMS == 3) {
-                    const int rzp = z + 1 == Lz ? r - (Lz - 1) * Ly : r + Ly;
-                    const int rzm = z == 0 ? r + (Lz - 1) * Ly : r - Ly;
-                    nb[4] = S[p * R + rzp];
-                    nb[5] = S[p * R + rzm];
+                    nb[4] = S[op + rg.rzp];
+                    nb[5] = S[op + rg.rzm];
                     if (HASJ) {
-                        jb[4] = Jb[(4 + p) * R + r];
-                        jb[5] = Jb[(4 + p) * R + rzm];
+                        jb[4] = Jb[4 * R + op + r];
+                        jb[5] = Jb[4 * R + op + rg.rzm];
                     }
                 }
                 // per-bond indicator: heat-bath J s_j = -1, Metropolis unsatisfied
@@ -211,7 +233,7 @@ __global__ __launch_bounds__(1024) void k_small_bits(SmallBitsArgs a)
                                a.seed_hi);
                     if ((lo.x & 0xFFFFFFu) < tlow[cls]) acc |= 1u << b;
                 }
-                S[p * R + r] = HB ? (~acc & 0xFFFFu) : (s ^ acc);
+                S[op + r] = HB ? (~acc & 0xFFFFu) : (s ^ acc);
             }
             __syncthreads();
         }
@@ -219,8 +241,7 @@ __global__ __launch_bounds__(1024) void k_small_bits(SmallBitsArgs a)
             // E = 2 (unsatisfied bonds) - DIMS N, M = N - 2 (down spins)
             long long unsat = 0, down = 0;
             for (int r = tid; r < R; r += nt) {
-                const int y = r % Ly, z = r / Ly;
-                const int ryp = y + 1 == Ly ? r - y : r + 1;
+                const RowGeo rg = r == tid ? g0 : row_geo(r, Ly, Lz);
                 const uint32_t s0 = S[r], s1 = S[R + r];
                 const uint32_t j00 = HASJ ? Jb[r] : 0u, j01 = HASJ ? Jb[R + r] : 0u;
                 // + x bonds: even site 2i to odd i, odd site 2i + 1 to even i + 1
@@ -228,11 +249,9 @@ __global__ __launch_bounds__(1024) void k_small_bits(SmallBitsArgs a)
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
                     const uint32_t sp = p ? s1 : s0;
-                    u += __popc((sp ^ S[p * R + ryp] ^ (HASJ ? Jb[(2 + p) * R + r] : 0u)) & 0xFFFFu);
-                    if (DIMS == 3) {
-                        const int rzp = z + 1 == Lz ? r - (Lz - 1) * Ly : r + Ly;
-                        u += __popc((sp ^ S[p * R + rzp] ^ (HASJ ? Jb[(4 + p) * R + r] : 0u)) & 0xFFFFu);
-                    }
+                    u += __popc((sp ^ S[p * R + rg.ryp] ^ (HASJ ? Jb[(2 + p) * R + r] : 0u)) & 0xFFFFu);
+                    if (DIMS == 3)
+                        u += __popc((sp ^ S[p * R + rg.rzp] ^ (HASJ ? Jb[(4 + p) * R + r] : 0u)) & 0xFFFFu);
                 }
                 unsat += u;
                 down += __popc(s0) + __popc(s1);
