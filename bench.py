@@ -32,6 +32,10 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_FLIP = 2.0
 SWEEPS_PER_STEP = 100
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile2d_L4096x3_traffic.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "k_tile2d_L4096x3_valu.txt")
+# integer VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD
+# every 4 cycles (16 lanes per cycle), at 2.4 GHz
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 KERNEL_SRC = os.path.join(ROOT, "paper_1709_04394_amd", "csrc", "k_tile2d.hip")
 
 
@@ -59,20 +63,44 @@ def measured_traffic(plan):
     summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by what
     the counter reads for a plain copy of known size), or None when that
     summary was taken on another kernel source or launch shape."""
+    kv = _kv_for_kernel(TRAFFIC_FILE, plan)
+    if kv is None:
+        return None
+    return 1024.0 * (float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"]) +
+                     float(kv["write_kib_per_launch"]) * float(kv["write_scale"]))
+
+
+def _kv_for_kernel(path, plan):
+    """key: value lines of a committed counter summary, or None when it was
+    taken on another kernel source or launch shape."""
     import hashlib
 
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     if kv.get("kernel_source_sha256") != src or kv.get("tile_plan") != "%d,%d,%d" % tuple(plan):
         return None
-    return 1024.0 * (float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"]) +
-                     float(kv["write_kib_per_launch"]) * float(kv["write_scale"]))
+    return kv
+
+
+def measured_valu(plan, launch_s):
+    """VALU issue of the dominant kernel: wave64 VALU instructions per launch
+    (SQ_INSTS_VALU from the committed counter summary) over the live average
+    launch duration, against the chip's integer VALU issue peak."""
+    kv = _kv_for_kernel(VALU_FILE, plan)
+    if kv is None:
+        return None
+    n = float(kv["valu_insts_per_launch"])
+    rate = n / launch_s
+    return {"instructions_per_launch": n, "achieved": rate, "peak": VALU_PEAK_WAVE_INSTS,
+            "unit": "wave64 VALU instructions/s", "frac": rate / VALU_PEAK_WAVE_INSTS,
+            "note": "peak = 256 CUs x 4 SIMDs x one wave64 instruction per 4 cycles x 2.4 GHz; multi-cycle "
+                    "instructions (64-bit multiplies in Philox) occupy a SIMD longer, so this undercounts issue"}
 
 
 def _events_ms(torch, fn, reps):
@@ -360,6 +388,7 @@ def main():
                       "per-sweep E, M per launch" % (K, K),
             "avg_launch_us": launch_ms * 1e3, "tile_plan": {"H": H, "K": K, "threads": T},
             "algorithmic_bytes_per_launch": BYTES_PER_FLIP * 3 * L * L * K}
+    valu = measured_valu(plan, launch_ms * 1e-3)
 
     out = {"metric": "spin flips/ns, % roofline (2D Ising L=4096)", "value": value, "unit": "spin flips/ns",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms / a.steps,
@@ -368,7 +397,7 @@ def main():
            "config": {"workload": "2D Ising 4096x4096 periodic, int8 spins, checkerboard Metropolis, "
                                   "beta in {0.40, beta_c, 0.50}, per-sweep E and M",
                       "L": L, "lattices": 3, "betas": list(BETAS), "sweeps_per_step": SWEEPS_PER_STEP},
-           "roofline": roof}
+           "roofline": roof, "valu": valu}
     if not a.no_rows:
         out["rows"] = row_measurements(torch, mcs, ctx, dev)
     if a.muca:

@@ -91,13 +91,11 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t v, int lane)
 template <int DIMS, bool MEASURE, bool HB, bool HASJ>
 __global__ __launch_bounds__(256) void k_msc(MscArgs a)
 {
-    __shared__ uint32_t tm[64];   // [plane][class] threshold bits as masks
     __shared__ uint32_t tlow[8];
     __shared__ long long red[2][64];
     constexpr int Z = 2 * DIMS;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l = blockIdx.y;
-    if (tid < 64) tm[tid] = ((a.top[tid & 7] >> (tid >> 3)) & 1u) ? ~0u : 0u;
     if (tid < 8) tlow[tid] = a.low[tid];
     if (MEASURE && tid < 128) red[tid >> 6][tid & 63] = 0;
     __syncthreads();
@@ -164,26 +162,45 @@ __global__ __launch_bounds__(256) void k_msc(MscArgs a)
 #pragma unroll
         for (int g = 0; g < 4; ++g)
             B[g] = philox(make_uint4((uint32_t)((j0 >> 4) + g), rep, a.sweep_lo, a.w3), a.seed_lo, a.seed_hi);
+        // One indicator word per class (heat-bath d = 0..6; Metropolis a below
+        // z/2, larger a being accepted outright); a plane's threshold word is the
+        // OR of the indicators of the classes whose threshold has that bit, the
+        // bits being uniform (argument block), so only the indicator words stay
+        // live across the planes.
+        constexpr int NC = HB ? 7 : DIMS;  // Metropolis: a = 0 .. z/2 - 1
+        uint64_t onehot[7];
+        uint32_t tp[7];
+        {
+            const uint64_t n0 = ~c0, n1 = ~c1, n2 = ~c2;
+            onehot[0] = n2 & n1 & n0;
+            onehot[1] = n2 & n1 & c0;
+            onehot[2] = n2 & c1 & n0;
+            onehot[3] = n2 & c1 & c0;
+            onehot[4] = c2 & n1 & n0;
+            onehot[5] = c2 & n1 & c0;
+            onehot[6] = c2 & c1 & n0;
+            // the thresholds' top bytes, marked as redefined per task so the plane
+            // masks below are formed where used, not hoisted out of the task loop
+            // into scalar registers (where they would spill)
+#pragma unroll
+            for (int d = 0; d < NC; ++d) {
+                tp[d] = a.top[d];
+                asm volatile("" : "+s"(tp[d]));
+            }
+        }
         uint64_t lt = 0ull, eq = ~0ull;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const uint64_t rowk = (uint64_t)plane_pair(B[0], B[1], k) | ((uint64_t)plane_pair(B[2], B[3], k) << 32);
             const uint64_t X = transpose64(rowk, lane);
-            const uint4 ml = *(const uint4 *)&tm[8 * k];
-            const uint64_t M0 = ml.x ? ~0ull : 0ull, M1 = ml.y ? ~0ull : 0ull, M2 = ml.z ? ~0ull : 0ull;
-            uint64_t T;
-            if (HB) {
-                const uint4 mh = *(const uint4 *)&tm[8 * k + 4];
-                const uint64_t M3 = ml.w ? ~0ull : 0ull, M4 = mh.x ? ~0ull : 0ull, M5 = mh.y ? ~0ull : 0ull,
-                               M6 = mh.z ? ~0ull : 0ull;
-                const uint64_t m01 = (c0 & M1) | (~c0 & M0), m23 = (c0 & M3) | (~c0 & M2);
-                const uint64_t m45 = (c0 & M5) | (~c0 & M4);
-                const uint64_t lo4 = (c1 & m23) | (~c1 & m01), hi4 = (c1 & M6) | (~c1 & m45);
-                T = (c2 & hi4) | (~c2 & lo4);
-            } else {
-                const uint64_t m01 = (c0 & M1) | (~c0 & M0);
-                T = (c1 & M2) | (~c1 & m01);
+            uint32_t tlo = 0u, thi = 0u;
+#pragma unroll
+            for (int d = 0; d < NC; ++d) {
+                const uint32_t m = ((tp[d] >> k) & 1u) ? ~0u : 0u;
+                tlo |= (uint32_t)onehot[d] & m;
+                thi |= (uint32_t)(onehot[d] >> 32) & m;
             }
+            const uint64_t T = ((uint64_t)thi << 32) | tlo;
             lt = (~X & T) | (~X & lt) | (T & lt);
             eq = eq & ~(X ^ T);
         }
