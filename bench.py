@@ -216,6 +216,19 @@ def lng_error(lng_est, lng_ex):
     return float(np.max(np.abs(a + c - b)))
 
 
+def lng_error_best_constant(lng_est, lng_ex):
+    """max |ln g_est + c - ln g_exact| over the window levels with states, for
+    the best constant c (the method fixes ln g only up to a constant): half the
+    spread of the differences."""
+    import numpy as np
+
+    m = np.isfinite(lng_ex)
+    if not np.all(np.isfinite(lng_est[m])):
+        return float("inf")
+    d = lng_ex[m] - lng_est[m]
+    return float((d.max() - d.min()) / 2)
+
+
 def muca_comparison(torch, mcs, ctx, sizes, prod_max):
     """Learned vs plain initial weights: train on the method's converged
     weights at L = 16, 24, 32, 48, compare total sweeps to a flat histogram at
@@ -248,7 +261,9 @@ def muca_comparison(torch, mcs, ctx, sizes, prod_max):
                         "sweeps_per_walker": int(r["sweeps_per_walker"]), "total_sweeps": int(r["total_sweeps"]),
                         "prep_sweeps_per_walker": int(r["prep_sweeps_per_walker"]),
                         "seconds": round(r["seconds"], 2), "final_min_over_max": round(float(r["min_over_max"]), 4),
-                        "max_abs_lng_error": lng_error(r["lng"], ex) if r["lng"] is not None else None}
+                        "max_abs_lng_error": lng_error(r["lng"], ex) if r["lng"] is not None else None,
+                        "max_abs_lng_error_best_constant": lng_error_best_constant(r["lng"], ex)
+                        if r["lng"] is not None else None}
         row["learned"]["fallback"] = bool(c["learned"]["fallback"])
         init_err = lng_error(-c["lnW_init"], ex)
         row["learned"]["initial_max_abs_lnW_error"] = init_err

@@ -98,3 +98,147 @@ def compare(ctx, L, params, seed=None, prod_sweeps=0, **kw):
     learned = run_arm(ctx, L, seed, lnW_init=None if fallback else lnW0, prod_sweeps=prod_sweeps, **kw)
     learned["fallback"] = bool(fallback)
     return {"plain": plain, "learned": learned, "lnW_init": lnW0}
+
+
+# ---------------------------------------------------------------------------
+# Long production at fixed converged weights, split over independent runs.
+# At L = 128 the error of ln g = ln H - ln W is set by how many times the
+# walkers cross the energy window, so reaching a given accuracy takes hundreds
+# of thousands of sweeps per walker; separate runs (each from its own walker
+# start and burn-in, different seeds) add their histograms.
+
+def production(ctx, L, lnW, seed, burn, sweeps, walkers=WALKERS, chunk=1000, label=""):
+    """Recorded histogram of `sweeps` multicanonical sweeps per walker at fixed
+    weights lnW, after a stratified walker start and `burn` unrecorded sweeps;
+    sweeps are numbered from 0 over burn-in and production.  Returns the int64
+    histogram over the window levels."""
+    from . import MUCA_STRATIFIED
+
+    spins, E = ctx.muca_start(L, walkers, seed, start=MUCA_STRATIFIED)
+    ws = ctx.muca_workspace(L, walkers)
+    H = torch.zeros(L * L // 2 + 1, dtype=torch.int64, device=ctx.device)
+    t0 = time.perf_counter()
+    last, sw = t0, 0
+    for rec, n in ((False, burn), (True, sweeps)):
+        done = 0
+        while done < n:
+            k = min(chunk, n - done)
+            ctx.muca_sweeps(L, spins, E, lnW, seed, sw, k, rec, H=H if rec else None, ws=ws)
+            done += k
+            sw += k
+            torch.cuda.synchronize()
+            now = time.perf_counter()
+            if now - last > 20:
+                last = now
+                print("%s seed %d: %s %d/%d, %.0f s" % (label, seed, "production" if rec else "burn-in", done, n,
+                                                       now - t0), file=sys.stderr, flush=True)
+    return H.cpu().numpy()
+
+
+def lng_errors(H, lnW, lng_exact):
+    """max |ln g_est - ln g_exact| over the levels with states, ln g_est =
+    ln H - ln W: (a) after matching the normalisations (log-sum-exp over those
+    levels), (b) after the best additive constant (half the spread of the
+    differences; the method fixes ln g only up to a constant)."""
+    m = np.isfinite(lng_exact)
+    with np.errstate(divide="ignore"):
+        lng = np.where(H > 0, np.log(np.maximum(H, 1)), -np.inf) - lnW
+    if not np.all(np.isfinite(lng[m])):
+        return float("inf"), float("inf")
+    a, b = lng[m], lng_exact[m]
+    c = np.logaddexp.reduce(b) - np.logaddexp.reduce(a)
+    d = b - a
+    return float(np.max(np.abs(a + c - b))), float((d.max() - d.min()) / 2)
+
+
+def main(argv=None):
+    """Stages of the L = 128 comparison run to the accuracy target:
+      converge --L 128 --out DIR        training sizes, MLP, both arms to a flat
+                                        histogram; DIR/weights.npz, DIR/converge.json
+      produce --dir DIR --arm A --seed S --burn B --sweeps P
+                                        one production run; DIR/H_A_S.npy
+      score --dir DIR --exact FILE      errors per run and per arm (runs summed)"""
+    import argparse
+    import glob
+    import json
+    import os
+
+    p = argparse.ArgumentParser(prog="python -m paper_1709_04394_amd.learned_muca")
+    sub = p.add_subparsers(dest="stage", required=True)
+    c = sub.add_parser("converge")
+    c.add_argument("--L", type=int, default=128)
+    c.add_argument("--out", required=True)
+    q = sub.add_parser("produce")
+    q.add_argument("--dir", required=True)
+    q.add_argument("--arm", choices=("plain", "learned"), required=True)
+    q.add_argument("--seed", type=int, required=True)
+    q.add_argument("--burn", type=int, default=20000)
+    q.add_argument("--sweeps", type=int, required=True)
+    q.add_argument("--refined", action="store_true",
+                   help="run at ln W = -ln g estimated from the arm's earlier runs (summed), saved as "
+                        "DIR/weights_refined_A.npy; the histogram goes to DIR/HR_A_S.npy")
+    s = sub.add_parser("score")
+    s.add_argument("--dir", required=True)
+    s.add_argument("--exact", required=True, help="stored exact ln g over the window levels (text)")
+    a = p.parse_args(argv)
+
+    if a.stage == "score":
+        w = np.load(os.path.join(a.dir, "weights.npz"))
+        conv = json.load(open(os.path.join(a.dir, "converge.json")))
+        ex = np.loadtxt(a.exact)
+        out = {}
+        for arm in ("plain", "learned"):
+            files = sorted(glob.glob(os.path.join(a.dir, "H_%s_*.npy" % arm)))
+            if not files:
+                continue
+            runs = {os.path.basename(f)[:-4]: lng_errors(np.load(f), w["lnW_" + arm], ex) for f in files}
+            Hs = sum(np.load(f) for f in files)
+            lse, best = lng_errors(Hs, w["lnW_" + arm], ex)
+            out[arm] = dict(conv[arm], runs=runs, production_records=int(Hs.sum()),
+                            max_abs_lng_error=lse, max_abs_lng_error_best_constant=best)
+            rf = os.path.join(a.dir, "weights_refined_%s.npy" % arm)
+            rfiles = sorted(glob.glob(os.path.join(a.dir, "HR_%s_*.npy" % arm)))
+            if rfiles and os.path.exists(rf):
+                lnWr = np.load(rf)
+                out[arm]["refined_runs"] = {os.path.basename(f)[:-4]: lng_errors(np.load(f), lnWr, ex)
+                                            for f in rfiles}
+        print(json.dumps(out, indent=1))
+        return
+
+    from . import Context
+
+    ctx = Context(0)
+    if a.stage == "converge":
+        os.makedirs(a.out, exist_ok=True)
+        lnW_by_L, _ = training_weights(ctx)
+        params, log = train_network(ctx, lnW_by_L)
+        r = compare(ctx, a.L, params, prod_sweeps=0)
+        conv = {arm: {k: (bool(r[arm][k]) if k == "converged" else float(r[arm][k]))
+                      for k in ("iterations", "sweeps_per_walker", "total_sweeps", "seconds", "min_over_max",
+                                "converged")} for arm in ("plain", "learned")}
+        conv["mlp_loss"] = [float(log[0]), float(log[-1])]
+        np.savez(os.path.join(a.out, "weights.npz"), lnW_plain=r["plain"]["lnW"], lnW_learned=r["learned"]["lnW"],
+                 lnW_init=r["lnW_init"], L=a.L)
+        json.dump(conv, open(os.path.join(a.out, "converge.json"), "w"))
+        print(json.dumps(conv), flush=True)
+    else:
+        w = np.load(os.path.join(a.dir, "weights.npz"))
+        L = int(w["L"])
+        lnW = w["lnW_" + a.arm]
+        if a.refined:
+            files = sorted(glob.glob(os.path.join(a.dir, "H_%s_*.npy" % a.arm)))
+            if not files:
+                raise SystemExit("no earlier runs of arm %s in %s" % (a.arm, a.dir))
+            Hs = sum(np.load(f) for f in files)
+            if np.any(Hs == 0):
+                raise SystemExit("an earlier run left a window level empty")
+            lnW = -(np.log(Hs) - lnW)
+            lnW = lnW - lnW[-1]
+            np.save(os.path.join(a.dir, "weights_refined_%s.npy" % a.arm), lnW)
+        H = production(ctx, L, lnW, a.seed, a.burn, a.sweeps, label=a.arm)
+        np.save(os.path.join(a.dir, "%s_%s_%d.npy" % ("HR" if a.refined else "H", a.arm, a.seed)), H)
+        print(json.dumps({"arm": a.arm, "seed": a.seed, "burn": a.burn, "sweeps": a.sweeps}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
