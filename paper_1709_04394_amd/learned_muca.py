@@ -230,10 +230,15 @@ def main(argv=None):
             if not files:
                 raise SystemExit("no earlier runs of arm %s in %s" % (a.arm, a.dir))
             Hs = sum(np.load(f) for f in files)
-            if np.any(Hs == 0):
-                raise SystemExit("an earlier run left a window level empty")
-            lnW = -(np.log(Hs) - lnW)
-            lnW = lnW - lnW[-1]
+            # levels never visited have no states (E = -2N + 4 on the torus): no
+            # move enters them, so their weight is copied from the level below
+            seen = Hs > 0
+            if not seen[0] or not seen[-1]:
+                raise SystemExit("an earlier run left an end of the window unvisited")
+            lnWr = np.where(seen, lnW - np.log(np.maximum(Hs, 1)), 0.0)
+            for k in np.flatnonzero(~seen):
+                lnWr[k] = lnWr[k - 1]
+            lnW = lnWr - lnWr[-1]
             np.save(os.path.join(a.dir, "weights_refined_%s.npy" % a.arm), lnW)
         H = production(ctx, L, lnW, a.seed, a.burn, a.sweeps, label=a.arm)
         np.save(os.path.join(a.dir, "%s_%s_%d.npy" % ("HR" if a.refined else "H", a.arm, a.seed)), H)
