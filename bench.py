@@ -192,6 +192,42 @@ def row_measurements(torch, mcs, ctx, dev):
     el = _t.perf_counter() - t0
     rows["muca_4096_walkers_L128"] = {"value": Wm * Lm * Lm * 4 / (el * 1e9), "unit": "single-site updates/ns",
                                       "ms_per_sweep": el * 250.0}
+    del spins, E, wsm, H
+
+    # MLP for initial weights: full-batch Adam epochs (hand-written forward,
+    # backward and update kernels, replayed graph) on a training set shaped
+    # like the one of converged weights at L = 16, 24, 32, 48 (here the smooth
+    # synthetic ln W = -N h(k / 2N), h the binary entropy), then the
+    # prediction of initial ln W at L = 128
+    def synth_lnW(Lt):
+        N = Lt * Lt
+        x = np.arange(N // 2 + 1) / (2.0 * N)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            h = -np.where(x > 0, x * np.log(np.maximum(x, 1e-300)), 0.0) - (1 - x) * np.log1p(-x)
+        return -N * h
+
+    X, Y = ctx.mlp_training_set({Lt: synth_lnW(Lt) for Lt in (16, 24, 32, 48)})
+    Xd, Yd = torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)
+    params = ctx.mlp_init(1)
+    ctx.mlp_train(params, Xd, Yd, 500)
+    torch.cuda.synchronize()
+    epochs = 5000
+    t0 = _t.perf_counter()
+    ctx.mlp_train(params, Xd, Yd, epochs)
+    torch.cuda.synchronize()
+    el = _t.perf_counter() - t0
+    n = int(Yd.numel())
+    # 2 -> 64 -> 64 -> 1: forward 2 (2*64 + 64*64 + 64) flop per sample, backward
+    # about twice that (input gradients of the first layer are not needed)
+    flop = 3 * 2 * (2 * 64 + 64 * 64 + 64) * n * epochs
+    t1 = _t.perf_counter()
+    ctx.mlp_lnw_init(params, 128)
+    el_pred = _t.perf_counter() - t1
+    rows["mlp_train_2-64-64-1"] = {"value": epochs / el, "unit": "epochs/s", "samples": n,
+                                   "us_per_epoch": el / epochs * 1e6, "predict_L128_ms": el_pred * 1e3,
+                                   "roofline": {"bound": "alu", "achieved": flop / el / 1e12, "peak": 157.3,
+                                                "unit": "TFLOP/s", "frac": flop / el / 1e12 / 157.3},
+                                   "note": "launch-bound: 4417 parameters, a few thousand samples per epoch"}
     return rows
 
 
