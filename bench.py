@@ -357,7 +357,7 @@ def cpu_baseline(target_s):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X; "
+        print("bench.py measures one GPU only (the workload is one MI355X's share); "
               "--gpus %d is not supported" % a.gpus, file=sys.stderr)
         sys.exit(2)
     if a.copy_probe:
