@@ -12,6 +12,11 @@ simulations", Eq. muca, Eq. weight_modification, count-again rule).
 * Acceptance table: ceil(min(1, W(E')/W(E)) 2^32).
 * Stratified walker starts: the integer disorder level equals its rounded
   closed form, and the starting energies follow -2N (1 - c/128)^2.
+* Walker preparation: the group temperatures are the weights' slope -d lnW/dE
+  (beta0 for canonical weights, -2aE at the group's level for ln W = a E^2,
+  0 for flat or rising weights); walkers prepared at canonical weights
+  reproduce Kaufman's exact energy at L = 16, and their recorded energies equal
+  their measured ones.
 """
 import math
 
@@ -143,3 +148,63 @@ def test_stratified_start_spreads_energies():
             s[(np.add.outer(np.arange(L), np.arange(L)) % 2) == 1] *= -1
             s = s.reshape(-1)
         assert np.array_equal(hs[w * N:(w + 1) * N], s)
+
+
+def _levels_E(L):
+    N = L * L
+    return np.array([4.0 * k - 2.0 * N for k in range(oracle.muca_levels(L))])
+
+
+def _target_levels(L, G):
+    # round-half-up of (g + 1/2) K / G, clamped to 2 .. K - 1, in exact integers
+    K = oracle.muca_levels(L) - 1
+    out = []
+    for g in range(G):
+        num, den = (2 * g + 1) * K, 2 * G
+        k = (2 * num + den) // (2 * den)
+        out.append(min(max(k, 2), K - 1))
+    return out
+
+
+@pytest.mark.parametrize("L,walkers", [(8, 100), (16, 4096), (12, 5)])
+def test_prep_betas_of_canonical_weights(L, walkers):
+    # ln W = -beta0 E: every group's slope is beta0
+    beta0 = 0.37
+    lnW = -beta0 * _levels_E(L)
+    b = oracle.muca_prep_betas(L, walkers, lnW)
+    assert len(b) == min(oracle.MUCA_PREP_GROUPS, walkers)
+    assert np.allclose(b, beta0, rtol=0, atol=1e-12)
+
+
+def test_prep_betas_of_quadratic_weights():
+    # ln W = a E^2: the central difference is exact, -d lnW/dE = -2 a E at the
+    # group's level (E <= 0 in the window, so positive)
+    L, a = 16, 3e-4
+    E = _levels_E(L)
+    b = oracle.muca_prep_betas(L, 4096, a * E * E)
+    want = [-2.0 * a * E[k] for k in _target_levels(L, 16)]
+    assert np.allclose(b, want, rtol=1e-12, atol=1e-12)
+
+
+def test_prep_betas_flat_and_rising_weights_are_zero():
+    L = 8
+    assert oracle.muca_prep_betas(L, 64, np.zeros(oracle.muca_levels(L))) == [0.0] * 16
+    # weights rising with E (negative slope temperature) are clamped to 0
+    assert oracle.muca_prep_betas(L, 64, 0.5 * _levels_E(L)) == [0.0] * 16
+
+
+def test_prepare_gives_canonical_walkers():
+    # canonical weights at beta0 = 0.3: prepared walkers sample P_beta0, so the
+    # mean energy per site approaches Kaufman's exact u(beta0) at L = 16, and
+    # each recorded energy equals the walker's measured energy
+    L, W, beta0 = 16, 256, 0.3
+    N = L * L
+    spins, E = oracle.muca_start(L, W, 91)
+    lnW = -beta0 * _levels_E(L)
+    oracle.muca_prepare(L, spins, E, 91, lnW, 120)
+    for w in range(0, W, 17):
+        em = oracle.measure(2, L, spins[w * N:(w + 1) * N])
+        assert E[w] == em[0]
+    assert np.all(E <= 0)
+    u, _ = exact.kaufman_u_cv(L, beta0)
+    assert abs(E.mean() / N - u) < 0.04, (E.mean() / N, u)
