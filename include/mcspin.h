@@ -34,6 +34,18 @@
  * Couplings (+-J model, Sec. "Disordered systems"): J[d][z][y][x] int8 +-1 is
  * the coupling of the bond (site, site + e_d), d = x, y(, z); NULL means J = 1.
  * Boundary conditions are periodic in every direction.
+ *
+ * Random numbers: Philox4x32-10 (key = seed as two 32-bit words, counter as
+ * given per call) yields a block of four 32-bit words w0..w3.  "Byte p of a
+ * block" (p = 0..15) below is not the p-th byte of those 16 bytes: it is the
+ * 8-bit number whose bit k (k = 0..7) is bit p of 16-bit half-word k of the
+ * block, half-word k being bits 16 (k mod 2) .. 16 (k mod 2) + 15 of word
+ * k / 2.  One block thus gives 16 bytes as eight bit-planes, the form the
+ * bit-sliced kernels consume.  "Word 0" is w0.  The tags in counter word 3
+ * (bits 24..31) are TAG_INIT = 1, TAG_SWEEP = 2, TAG_COUPLING = 3,
+ * TAG_RESAMPLE = 4, TAG_MUCA = 5, TAG_MLP_INIT = 6, TAG_SWEEP_LO = 7 (8 is
+ * reserved); bit 23 holds the half-sweep colour where one is given, bits
+ * 0..22 the high bits of a 64-bit sweep number.
  */
 #ifndef MCSPIN_H
 #define MCSPIN_H
@@ -103,12 +115,14 @@ int mc_init(mc_ctx *ctx, const mc_geom *geom, void *spins, int32_t start, uint64
 int mc_couplings(mc_ctx *ctx, const mc_geom *geom, int8_t *J, uint64_t seed, void *stream);
 
 /* Bytes of scratch mc_sweep can use to run several sweeps per fused launch:
- * two bit-packed copies of the lattices (count * Ly * Lx / 8 bytes each),
- * between which the launches of one call ping-pong; only the first launch
- * reads and only the last writes the caller's int8 lattices.  Non-zero for
- * 2D int8 geometries with Lx a multiple of 64 (at most 16384).  With a
- * smaller or NULL workspace mc_sweep runs the two half-sweeps as two in-place
- * launches; the results are identical either way.                          */
+ * two bit-packed copies of the lattices (count * Lz * Ly * Lx / 8 bytes
+ * each), between which the launches of one call ping-pong, and in 3D the
+ * couplings packed once per call (3 * Lz * Ly * Lx / 8 bytes); only the first
+ * launch reads and only the last writes the caller's int8 lattices.  Non-zero
+ * for int8 geometries with Lx a multiple of 64: 2D with Lx <= 16384, 3D with
+ * Lx <= 4096 and Ly, Lz >= 4.  With a smaller or NULL workspace mc_sweep uses
+ * kernels that need none (a whole small lattice per workgroup, or per-half-
+ * sweep launches); the results are identical either way.                   */
 size_t mc_sweep_workspace_bytes(const mc_geom *geom);
 
 /* nsweeps checkerboard sweeps (Sec. "Checkerboard scheme"): one sweep updates
