@@ -4,6 +4,9 @@ generation", counter-based generators).
 * Known answers: the oracle's Philox block equals rocRAND's host-side
   Philox4x32-10 engine (an independent implementation shipped with ROCm, built
   here from its header) for edge and random (key, counter) values.
+* The draws follow the documented counter layout (key = seed words; counter =
+  index, replica, sweep low word, tag << 24 | colour << 23 | sweep >> 32) and
+  the documented bit-plane gather of a block's byte.
 * The 32-bit draws assembled from two blocks are uniform (chi-square on the top
   byte and on the low bits), distinct streams are uncorrelated, and the 53-bit
   resampling variate lies in [0, 1).
@@ -106,3 +109,27 @@ def test_resample_u_range_and_mean():
     assert abs(u.mean() - 0.5) < 6 * np.sqrt(1 / 12 / u.size)
     # 53-bit grid
     assert np.all(u * 2.0 ** 53 == np.floor(u * 2.0 ** 53))
+
+
+def _gather_byte(block, p):
+    # the documented "byte p of a block": bit k is bit p of 16-bit half-word k,
+    # half-word k being bits 16 (k mod 2) .. +15 of word k / 2
+    return sum(((int(block[k >> 1]) >> (16 * (k & 1) + p)) & 1) << k for k in range(8))
+
+
+@pytest.mark.parametrize("seed,tag,replica,sweep,phase", [(11, oracle.TAG_SWEEP, 4, 8, 1),
+                                                          ((7 << 40) | 123, oracle.TAG_SWEEP, 65, (1 << 33) + 5, 0),
+                                                          (3, oracle.TAG_INIT, 9, 0, 0)])
+def test_draws_follow_the_documented_counter_layout(seed, tag, replica, sweep, phase):
+    # key = (seed low word, seed high word); counter = (index, replica, sweep low
+    # word, tag << 24 | phase << 23 | sweep >> 32); the top byte is the gathered
+    # byte of block j / 16, the low 24 bits word 0 of block j under TAG_SWEEP_LO
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    w3 = lambda t: (t << 24) | (phase << 23) | ((sweep >> 32) & 0x7FFFFF)
+    for j in list(range(40)) + [1000, 65535, 1 << 20]:
+        blk = oracle.philox([j >> 4, replica, sweep & 0xFFFFFFFF, w3(tag)], key)
+        assert oracle.draw_byte(seed, tag, j, replica, sweep, phase) == _gather_byte(blk, j & 15)
+        if tag == oracle.TAG_SWEEP:
+            lo = oracle.philox([j, replica, sweep & 0xFFFFFFFF, w3(oracle.TAG_SWEEP_LO)], key)
+            r = oracle.draw32(seed, tag, oracle.TAG_SWEEP_LO, j, replica, sweep, phase)
+            assert r == (_gather_byte(blk, j & 15) << 24) | (int(lo[0]) & 0xFFFFFF)
