@@ -47,3 +47,26 @@ def test_empty_level_is_infinite():
     H = H.copy()
     H[np.flatnonzero(m)[3]] = 0
     assert lm.lng_errors(H, lnW, ex) == (float("inf"), float("inf"))
+
+
+def test_score_stage_end_to_end(tmp_path, capsys):
+    # the command-line score stage on synthetic files: two runs of one arm whose
+    # summed histogram reproduces the exact ln g up to a constant, one that
+    # does not
+    import json
+
+    ex, H, lnW, m = _setup()
+    np.savez(tmp_path / "weights.npz", lnW_plain=lnW, lnW_learned=lnW, lnW_init=lnW, L=16)
+    conv = {arm: {"iterations": 1.0, "sweeps_per_walker": 10.0, "total_sweeps": 10.0, "seconds": 0.0,
+                  "min_over_max": 1.0, "converged": True} for arm in ("plain", "learned")}
+    (tmp_path / "converge.json").write_text(json.dumps(conv))
+    np.save(tmp_path / "H_plain_1.npy", H)
+    np.save(tmp_path / "H_plain_2.npy", 2 * H)
+    Hb = H.copy()
+    Hb[np.flatnonzero(m)[:10]] *= 2
+    np.save(tmp_path / "H_learned_1.npy", Hb)
+    lm.main(["score", "--dir", str(tmp_path), "--exact", GOLD])
+    out = json.loads(capsys.readouterr().out)
+    assert out["plain"]["max_abs_lng_error_best_constant"] < 1e-9
+    assert set(out["plain"]["runs"]) == {"H_plain_1", "H_plain_2"}
+    assert abs(out["learned"]["max_abs_lng_error_best_constant"] - np.log(2) / 2) < 1e-9
