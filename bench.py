@@ -199,7 +199,20 @@ def row_measurements(torch, mcs, ctx, dev):
     el = _t.perf_counter() - t0
     flips = 200 * 10 * R * sum(x * x for x in Ls)
     rows["pa_4x16384_L16-128_200steps"] = {"value": flips / (el * 1e9), "unit": "spin flips/ns", "seconds": el,
+                                           "groups": [ctx.get_pa_group(L) for L in Ls],
                                            "note": "whole blocking call: graph build, 200 steps, ln Z and histograms"}
+    # the same anneal after timing replicas per workgroup on its first 20 steps
+    t0 = _t.perf_counter()
+    G = ctx.tune_pa(Ls, R, 10, 17, beta, pops, ws=ws)
+    tune_s = _t.perf_counter() - t0
+    ctx.pa_anneal(Ls, R, 10, 17, beta, pops, step_first=1, nsteps=2, ws=ws)
+    t0 = _t.perf_counter()
+    ctx.pa_anneal(Ls, R, 10, 17, beta, pops, step_first=1, nsteps=200, ws=ws)
+    el = _t.perf_counter() - t0
+    rows["pa_4x16384_L16-128_200steps_tuned"] = {"value": flips / (el * 1e9), "unit": "spin flips/ns",
+                                                 "seconds": el, "groups": G, "tune_seconds": tune_s}
+    for L in Ls:
+        ctx.set_pa_group(L, 0)
     del pops, ws
 
     # multicanonical walkers: 4096 walkers of 128 x 128, sequential updates

@@ -228,6 +228,30 @@ size_t mc_pa_workspace_bytes(const mc_pa_args *args);
 int mc_pa_anneal(mc_ctx *ctx, const mc_pa_args *args, void *const *pop_spins, double *Ctot, double *lnQ,
                  double *lnZ, int64_t *hist, void *ws, size_t ws_bytes, void *stream);
 
+/* Launch shape of population annealing: replicas per workgroup G of the
+ * sweep kernel for populations of extent L (a per-context setting).  It
+ * changes speed only: every replica draws from its own Philox stream keyed
+ * by its replica id, so results are identical for every G.
+ * mc_set_pa_group: G in 1..64 with G * 2 L * max(1, L/64) * 4 bytes of LDS
+ *   at most 48 KB, else MC_E_RANGE; G = 0 restores the built-in rule (about
+ *   256 packed 32-bit words per workgroup).  MC_E_SHAPE for an L that
+ *   mc_pa_anneal rejects.
+ * mc_get_pa_group: the G in use for L (set, tuned or built-in).           */
+int mc_set_pa_group(mc_ctx *ctx, int32_t L, int32_t G);
+int mc_get_pa_group(mc_ctx *ctx, int32_t L, int32_t *G);
+
+/* Autotuner for G: for each population of args (extents must differ) it
+ * times, with a host clock around blocking calls, a fresh anneal of that
+ * population alone over the first min(step_first - 1 + nsteps, 20) steps of
+ * the schedule, for G in {G0/4, G0/2, G0, 2 G0, 4 G0} (G0 the built-in rule,
+ * candidates outside the limits above or above R skipped), best of two runs
+ * each, and keeps the fastest G in the context.  G_out: host [npop] or NULL.
+ * pop_spins[p] and ws are scratch (contents overwritten); ws must hold
+ * mc_pa_workspace_bytes of one population over those steps.  Synchronises
+ * `stream`.                                                               */
+int mc_tune_pa(mc_ctx *ctx, const mc_pa_args *args, void *const *pop_spins, void *ws, size_t ws_bytes,
+               int32_t *G_out, void *stream);
+
 /* ------------------------------------------------------------------------
  * Multicanonical simulation with parallel walkers (Sec. "Multicanonical
  * simulations": walkers share W(E); their histograms are added; Eq. muca,

@@ -141,6 +141,10 @@ _lib_fns = dict(
     mc_pa_anneal=_sig("mc_pa_anneal", _c.c_int, [_vp, _c.POINTER(PAArgs), _c.POINTER(_vp), _c.POINTER(_c.c_double),
                                                  _c.POINTER(_c.c_double), _c.POINTER(_c.c_double),
                                                  _c.POINTER(_c.c_int64), _vp, _c.c_size_t, _vp]),
+    mc_set_pa_group=_sig("mc_set_pa_group", _c.c_int, [_vp, _c.c_int32, _c.c_int32]),
+    mc_get_pa_group=_sig("mc_get_pa_group", _c.c_int, [_vp, _c.c_int32, _c.POINTER(_c.c_int32)]),
+    mc_tune_pa=_sig("mc_tune_pa", _c.c_int, [_vp, _c.POINTER(PAArgs), _c.POINTER(_vp), _vp, _c.c_size_t,
+                                             _c.POINTER(_c.c_int32), _vp]),
 )
 
 
@@ -295,6 +299,33 @@ class Context:
             out.append(hist[off:off + n].reshape(nsteps + 1, L * L + 1))
             off += n
         return dict(Ctot=Ctot[:, :nsteps], lnQ=lnQ[:, :nsteps], lnZ=lnZ, hist=out)
+
+    def set_pa_group(self, L, G):
+        """Replicas per workgroup for populations of extent L (0: built-in rule)."""
+        return self._check(_lib.mc_set_pa_group(self._h, L, G), "mc_set_pa_group")
+
+    def get_pa_group(self, L):
+        G = ctypes.c_int32()
+        self._check(_lib.mc_get_pa_group(self._h, L, ctypes.byref(G)), "mc_get_pa_group")
+        return G.value
+
+    def tune_pa(self, Ls, R, theta, seed, beta, pops, step_first=1, nsteps=None, ws=None):
+        """Time replicas per workgroup for each extent in Ls and keep the fastest;
+        pops and ws are overwritten.  Returns the chosen G per population."""
+        import numpy as np
+
+        nsteps = len(beta) - step_first if nsteps is None else nsteps
+        a, keep = self._pa_args(Ls, R, theta, seed, beta, step_first, nsteps)
+        if ws is None:
+            need = max(self.pa_workspace_bytes([L], R, theta, beta, 1, min(step_first - 1 + nsteps, 20))
+                       for L in Ls)
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=self.device)
+        ptrs = (_vp * len(Ls))(*[_vp(t.data_ptr()) for t in pops])
+        G = np.zeros(len(Ls), dtype=np.int32)
+        self._check(_lib.mc_tune_pa(self._h, ctypes.byref(a), ptrs, _ptr(ws), ws.numel() * ws.element_size(),
+                                    G.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream(self.device)),
+                    "mc_tune_pa")
+        return [int(g) for g in G]
 
     # ---------------------------------------------------------------------- MLP
     def mlp_init(self, seed):

@@ -28,6 +28,9 @@ struct mc_ctx {
     std::string last_error;
     // tuned launch shapes keyed by (dims, Lx, Ly, Lz, count)
     std::map<std::tuple<int, int, int, int, int>, mcs::TilePlan> tile_plans;
+    // population annealing: replicas per workgroup of the sweep kernel, keyed
+    // by the lattice extent L (set or tuned; absent means the built-in rule)
+    std::map<int, int> pa_groups;
     // stream on which launch sequences are recorded into hipGraphs (created
     // on first use, default priority, destroyed with the context)
     hipStream_t capture = nullptr;

@@ -2,6 +2,7 @@
 // Weight tables (FP64, libm exp, once per step), the per-step launch sequence
 // captured in one hipGraph, and ln Q / ln Z from the device's C_total.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <vector>
 
@@ -47,6 +48,27 @@ PaLayout pa_layout(const mc_pa_args *a)
     }
     lay.total = off;
     return lay;
+}
+
+int pa_words_per_row(int L) { return L >= 64 ? L / 64 : 1; }
+
+// Largest dynamic LDS a population may ask of the sweep kernel.  It stays
+// under the 64 KB that a launch gets without raising the kernel's limit
+// (the kernel's static LDS comes on top), and keeps every word index of the
+// packed lattices below 2^16, the width of the tie queue's index field.
+constexpr size_t kPaMaxGroupLds = 48 * 1024;
+
+size_t pa_group_lds(int L, int G) { return (size_t)G * 2 * L * pa_words_per_row(L) * 4; }
+
+bool pa_group_ok(int L, int G) { return G >= 1 && G <= 64 && pa_group_lds(L, G) <= kPaMaxGroupLds; }
+
+// Built-in rule: about 256 packed words per workgroup, one per thread.
+int pa_default_group(int L) { return std::max(1, std::min(64, 256 / (L * pa_words_per_row(L)))); }
+
+int pa_group_for(const mc_ctx *ctx, int L)
+{
+    const auto it = ctx->pa_groups.find(L);
+    return it != ctx->pa_groups.end() ? it->second : pa_default_group(L);
 }
 
 int check_pa(mc_ctx *ctx, const mc_pa_args *a)
@@ -124,8 +146,8 @@ int mc_pa_anneal(mc_ctx *ctx, const mc_pa_args *a, void *const *pop_spins, doubl
         P.N = P.L * P.L;
         P.R = a->R;
         P.Wb = std::min(32, P.L / 2);
-        P.nwr = P.L >= 64 ? P.L / 64 : 1;
-        P.G = std::max(1, std::min(64, 256 / (P.L * P.nwr)));
+        P.nwr = pa_words_per_row(P.L);
+        P.G = pa_group_for(ctx, P.L);
         P.blk0 = blocks;
         blocks += (P.R + P.G - 1) / P.G;
         P.x = (double *)(w + lay.x[p]);
@@ -235,6 +257,83 @@ int mc_pa_anneal(mc_ctx *ctx, const mc_pa_args *a, void *const *pop_spins, doubl
             lnQ[(size_t)p * a->nsteps + s_] = q;
             z[s_ + 1] = z[s_] + q;
         }
+    }
+    return MC_OK;
+}
+
+int mc_set_pa_group(mc_ctx *ctx, int32_t L, int32_t G)
+{
+    if (!ctx) return MC_E_INVAL;
+    if (!pa_L_ok(L)) return fail(ctx, MC_E_SHAPE, "L=%d is not a population annealing extent", L);
+    if (G == 0) {
+        ctx->pa_groups.erase(L);
+        return MC_OK;
+    }
+    if (!pa_group_ok(L, G))
+        return fail(ctx, MC_E_RANGE, "L=%d: %d replicas per workgroup exceed 64 or %zu bytes of LDS", L, G,
+                    kPaMaxGroupLds);
+    ctx->pa_groups[L] = G;
+    return MC_OK;
+}
+
+int mc_get_pa_group(mc_ctx *ctx, int32_t L, int32_t *G)
+{
+    if (!ctx || !G) return MC_E_INVAL;
+    if (!pa_L_ok(L)) return fail(ctx, MC_E_SHAPE, "L=%d is not a population annealing extent", L);
+    *G = pa_group_for(ctx, L);
+    return MC_OK;
+}
+
+int mc_tune_pa(mc_ctx *ctx, const mc_pa_args *a, void *const *pop_spins, void *ws, size_t ws_bytes, int32_t *G_out,
+               void *stream)
+{
+    if (!ctx) return MC_E_INVAL;
+    int rc = check_pa(ctx, a);
+    if (rc) return rc;
+    if (!pop_spins) return fail(ctx, MC_E_INVAL, "pop_spins is NULL");
+    for (int p = 0; p < a->npop; ++p) {
+        if (!pop_spins[p]) return fail(ctx, MC_E_INVAL, "pop_spins[%d] is NULL", p);
+        for (int q = 0; q < p; ++q)
+            if (a->L[q] == a->L[p]) return fail(ctx, MC_E_INVAL, "L=%d appears twice", a->L[p]);
+    }
+    // each population alone, over the first steps of the schedule, from a
+    // fresh start: every candidate runs identical work
+    const int nst = std::min(a->step_first - 1 + a->nsteps, 20);
+    if (nst < 1) return fail(ctx, MC_E_RANGE, "the schedule has no step to time");
+    for (int p = 0; p < a->npop; ++p) {
+        const int L = a->L[p];
+        const int32_t Lp[1] = {L};
+        mc_pa_args b = *a;
+        b.npop = 1;
+        b.L = Lp;
+        b.step_first = 1;
+        b.nsteps = nst;
+        if (ws_bytes < mc_pa_workspace_bytes(&b)) return fail(ctx, MC_E_WORKSPACE, "workspace too small for L=%d", L);
+        const size_t N = (size_t)L * L;
+        std::vector<double> C(nst), q(nst), z(nst + 1);
+        std::vector<int64_t> h((size_t)(nst + 1) * (N + 1));
+        const int G0 = pa_default_group(L);
+        int best = G0;
+        double best_t = 1e300;
+        const int cands[5] = {G0 / 4, G0 / 2, G0, 2 * G0, 4 * G0};
+        for (int G : cands) {
+            if (!pa_group_ok(L, G) || G > a->R) continue;
+            ctx->pa_groups[L] = G;
+            double t = 1e300;
+            for (int rep = 0; rep < 2; ++rep) {  // best of two: the first also warms up
+                const auto t0 = std::chrono::steady_clock::now();
+                rc = mc_pa_anneal(ctx, &b, pop_spins + p, C.data(), q.data(), z.data(), h.data(), ws, ws_bytes, stream);
+                const auto t1 = std::chrono::steady_clock::now();
+                if (rc) {
+                    ctx->pa_groups.erase(L);
+                    return rc;
+                }
+                t = std::min(t, std::chrono::duration<double>(t1 - t0).count());
+            }
+            if (t < best_t) best_t = t, best = G;
+        }
+        ctx->pa_groups[L] = best;
+        if (G_out) G_out[p] = best;
     }
     return MC_OK;
 }

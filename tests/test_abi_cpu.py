@@ -127,3 +127,47 @@ def test_mlp_training_set_matches_oracle(ctx):
     assert mcs._lib.mc_mlp_training_set(ctx, 3, Larr, parr, fp(X), fp(Y), cap, ctypes.byref(n)) == 0
     Larr[0] = 5
     assert mcs._lib.mc_mlp_training_set(ctx, 3, Larr, parr, fp(X), fp(Y), cap, ctypes.byref(n)) == mcs.MC_E_SHAPE
+
+
+def test_pa_group_setting(ctx):
+    """Replicas per workgroup of population annealing: the built-in rule, the
+    limits (G <= 64, at most 48 KB of packed lattices per workgroup) and reset."""
+    G = ctypes.c_int32()
+    builtin = {16: 16, 32: 8, 64: 4, 128: 1, 512: 1}
+    for L, g in builtin.items():
+        assert mcs._lib.mc_get_pa_group(ctx, L, ctypes.byref(G)) == 0 and G.value == g
+    assert mcs._lib.mc_set_pa_group(ctx, 16, 64) == 0
+    assert mcs._lib.mc_get_pa_group(ctx, 16, ctypes.byref(G)) == 0 and G.value == 64
+    assert mcs._lib.mc_get_pa_group(ctx, 32, ctypes.byref(G)) == 0 and G.value == 8  # other L untouched
+    assert mcs._lib.mc_set_pa_group(ctx, 16, 0) == 0
+    assert mcs._lib.mc_get_pa_group(ctx, 16, ctypes.byref(G)) == 0 and G.value == 16
+    assert mcs._lib.mc_set_pa_group(ctx, 16, 65) == mcs.MC_E_RANGE
+    assert mcs._lib.mc_set_pa_group(ctx, 16, -1) == mcs.MC_E_RANGE
+    # L = 128: 2 L * 2 words * 4 B = 2 KB per replica -> 24 fit in 48 KB, 25 do not
+    assert mcs._lib.mc_set_pa_group(ctx, 128, 24) == 0
+    assert mcs._lib.mc_set_pa_group(ctx, 128, 25) == mcs.MC_E_RANGE
+    # L = 512: 32 KB per replica -> only G = 1
+    assert mcs._lib.mc_set_pa_group(ctx, 512, 2) == mcs.MC_E_RANGE
+    assert mcs._lib.mc_set_pa_group(ctx, 12, 1) == mcs.MC_E_SHAPE
+    assert mcs._lib.mc_get_pa_group(ctx, 12, ctypes.byref(G)) == mcs.MC_E_SHAPE
+    assert mcs._lib.mc_get_pa_group(ctx, 16, None) == mcs.MC_E_INVAL
+    assert mcs._lib.mc_set_pa_group(None, 16, 4) == mcs.MC_E_INVAL
+
+
+def test_pa_tune_argument_errors(ctx):
+    Ls = (ctypes.c_int32 * 2)(16, 16)
+    beta = (ctypes.c_double * 3)(0.0, 0.1, 0.2)
+    a = mcs.PAArgs(2, Ls, 64, 1, 1, 1, 2, beta)
+    ptrs = (ctypes.c_void_p * 2)(FAKE, FAKE)
+    ws = FAKE
+    # the same extent twice
+    assert mcs._lib.mc_tune_pa(ctx, ctypes.byref(a), ptrs, ws, 1 << 30, None, None) == mcs.MC_E_INVAL
+    Ls[1] = 32
+    assert mcs._lib.mc_tune_pa(ctx, ctypes.byref(a), None, ws, 1 << 30, None, None) == mcs.MC_E_INVAL
+    # workspace too small
+    assert mcs._lib.mc_tune_pa(ctx, ctypes.byref(a), ptrs, ws, 16, None, None) == mcs.MC_E_WORKSPACE
+    # no step to time
+    a0 = mcs.PAArgs(2, Ls, 64, 1, 1, 1, 0, beta)
+    assert mcs._lib.mc_tune_pa(ctx, ctypes.byref(a0), ptrs, ws, 1 << 30, None, None) == mcs.MC_E_RANGE
+    G = ctypes.c_int32()
+    assert mcs._lib.mc_get_pa_group(ctx, 16, ctypes.byref(G)) == 0 and G.value == 16  # nothing was set

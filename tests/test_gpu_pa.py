@@ -102,3 +102,38 @@ def test_pa_full_config_free_energy_vs_kaufman(full_run):
             assert abs(est - ex) < 1e-3, (L, i, est, ex)
         # every histogram counts the whole population
         assert np.all(res["hist"][p].sum(axis=1) == R)
+
+
+@pytest.mark.parametrize("groups", [{4: 64, 16: 1, 64: 16, 128: 3}, {4: 7, 16: 64, 64: 1, 128: 24}])
+def test_pa_replicas_per_workgroup_do_not_change_results(ctx, groups):
+    """Any admissible replicas-per-workgroup setting gives the oracle's results
+    bit for bit (ragged last workgroup: R = 130 is a multiple of none of them)."""
+    Ls, R, theta, nsteps, seed = [4, 16, 64, 128], 130, 2, 3, 23
+    beta = np.array([i * 0.005 for i in range(nsteps + 1)])
+    try:
+        for L, G in groups.items():
+            ctx.set_pa_group(L, G)
+            assert ctx.get_pa_group(L) == G
+        pops = ctx.pa_population_tensors(Ls, R)
+        res = ctx.pa_anneal(Ls, R, theta, seed, beta, pops)
+    finally:
+        for L in groups:
+            ctx.set_pa_group(L, 0)
+    opops = [oracle.PAPopulation(L, R, p, seed).advance(beta, theta, nsteps) for p, L in enumerate(Ls)]
+    _compare(Ls, R, res, pops, opops, nsteps)
+
+
+def test_pa_tuner_picks_admissible_groups_and_keeps_results(ctx):
+    Ls, R, theta, nsteps, seed = [16, 128], 300, 1, 3, 29
+    beta = np.array([i * 0.005 for i in range(nsteps + 1)])
+    pops = ctx.pa_population_tensors(Ls, R)
+    try:
+        G = ctx.tune_pa(Ls, R, theta, seed, beta, pops)
+        assert G[0] in (4, 8, 16, 32, 64) and G[1] in (1, 2, 4), G
+        assert [ctx.get_pa_group(L) for L in Ls] == G
+        res = ctx.pa_anneal(Ls, R, theta, seed, beta, pops)
+    finally:
+        for L in Ls:
+            ctx.set_pa_group(L, 0)
+    opops = [oracle.PAPopulation(L, R, p, seed).advance(beta, theta, nsteps) for p, L in enumerate(Ls)]
+    _compare(Ls, R, res, pops, opops, nsteps)
