@@ -211,8 +211,8 @@ def row_measurements(torch, mcs, ctx, dev):
     el = _t.perf_counter() - t0
     rows["pa_4x16384_L16-128_200steps_tuned"] = {"value": flips / (el * 1e9), "unit": "spin flips/ns",
                                                  "seconds": el, "groups": G, "tune_seconds": tune_s}
-    for L in Ls:
-        ctx.set_pa_group(L, 0)
+    for Lp in Ls:
+        ctx.set_pa_group(Lp, 0)
     del pops, ws
 
     # multicanonical walkers: 4096 walkers of 128 x 128, sequential updates
