@@ -1,6 +1,7 @@
 // internal.hpp -- host-side helpers shared by the ABI translation units.
 #pragma once
 
+#include <atomic>
 #include <cstdarg>
 #include <cstddef>
 #include <map>
@@ -41,6 +42,27 @@ struct mc_ctx {
 };
 
 namespace mcs {
+
+// Raises one kernel's dynamic-LDS limit, once per device (the attribute
+// belongs to the device's copy of the kernel).  One function-local static
+// per kernel instance; safe when several host threads launch at once.
+class LdsLimit {
+  public:
+    hipError_t ensure(const void *kernel, int bytes)
+    {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        const uint64_t bit = dev >= 0 && dev < 64 ? (uint64_t)1 << dev : 0;
+        if (bit && (done_.load(std::memory_order_acquire) & bit)) return hipSuccess;
+        e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e == hipSuccess && bit) done_.fetch_or(bit, std::memory_order_release);
+        return e;
+    }
+
+  private:
+    std::atomic<uint64_t> done_{0};
+};
 
 int fail(mc_ctx *ctx, int code, const char *fmt, ...);
 int device_check(mc_ctx *ctx, hipError_t e, const char *what);

@@ -377,23 +377,15 @@ static hipError_t launch_muca_L(const MucaArgs &a, hipStream_t s)
     constexpr int K = L * L / 2;
     if constexpr (L % 32 == 0) {
         const size_t lds = (size_t)(K + 1) * 16 + (size_t)(K / 2 + 1) * 4;
-        static bool attr_set = false;
-        if (!attr_set) {
-            hipError_t e =
-                hipFuncSetAttribute((const void *)k_muca_w<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-            attr_set = true;
-        }
+        static LdsLimit lim;
+        const hipError_t e = lim.ensure((const void *)k_muca_w<L>, (int)lds);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_muca_w<L>, dim3((a.W + 63) / 64), dim3(64), lds, s, a);
     } else {
         const size_t lds = (size_t)(K + 1) * 4 * 4;
-        static bool attr_set = false;
-        if (!attr_set) {
-            hipError_t e =
-                hipFuncSetAttribute((const void *)k_muca<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-            attr_set = true;
-        }
+        static LdsLimit lim;
+        const hipError_t e = lim.ensure((const void *)k_muca<L>, (int)lds);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_muca<L>, dim3((a.W + 63) / 64), dim3(64), lds, s, a);
     }
     return hipGetLastError();

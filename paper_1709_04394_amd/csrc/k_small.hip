@@ -247,12 +247,11 @@ hipError_t launch_small(const SweepCall &c, int8_t *spins, uint64_t sweep0, int 
     a.em_stride = em_stride;
     const bool hj = c.J != nullptr;
     const size_t lds = small_lds_bytes(c.g, hj);
-    static bool attr[2] = {false, false};
-    if (!attr[hj ? 1 : 0]) {
-        const hipError_t e = hipFuncSetAttribute(hj ? (const void *)k_small<true> : (const void *)k_small<false>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    static LdsLimit lim[2];
+    {
+        const hipError_t e =
+            lim[hj ? 1 : 0].ensure(hj ? (const void *)k_small<true> : (const void *)k_small<false>, 150 * 1024);
         if (e != hipSuccess) return e;
-        attr[hj ? 1 : 0] = true;
     }
     if (hj) hipLaunchKernelGGL(k_small<true>, dim3((unsigned)c.g.count), dim3(1024), lds, s, a);
     else hipLaunchKernelGGL(k_small<false>, dim3((unsigned)c.g.count), dim3(1024), lds, s, a);

@@ -294,13 +294,10 @@ bool small_bits_supported(const SweepCall &c, int layout)
 template <int DIMS, bool HB, bool HASJ>
 static hipError_t launch_sb(const SmallBitsArgs &a, size_t lds, hipStream_t s)
 {
-    static bool attr = false;
-    if (!attr) {
-        const hipError_t e =
-            hipFuncSetAttribute((const void *)k_small_bits<DIMS, HB, HASJ>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                128 * 1024);
+    static LdsLimit lim;
+    {
+        const hipError_t e = lim.ensure((const void *)k_small_bits<DIMS, HB, HASJ>, 128 * 1024);
         if (e != hipSuccess) return e;
-        attr = true;
     }
     hipLaunchKernelGGL((k_small_bits<DIMS, HB, HASJ>), dim3((unsigned)a.g.count), dim3(1024), lds, s, a);
     return hipGetLastError();

@@ -423,13 +423,11 @@ static hipError_t launch3(const Tile3DArgs &a, int H, int count, int threads, hi
 {
     const size_t lds = tile3d_lds_bytes(a.Lx, H, K, HASJ);
     dim3 grid((unsigned)(a.nty * a.ntz), (unsigned)count);
-    static bool attr[2] = {false, false};
-    const int mi = a.EM ? 1 : 0;
-    if (!attr[mi]) {
+    static LdsLimit lim[2];
+    {
         const void *f = a.EM ? (const void *)k_tile3d<K, true, HB, HASJ> : (const void *)k_tile3d<K, false, HB, HASJ>;
-        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 98304);
+        const hipError_t e = lim[a.EM ? 1 : 0].ensure(f, 98304);
         if (e != hipSuccess) return e;
-        attr[mi] = true;
     }
     if (a.EM) hipLaunchKernelGGL((k_tile3d<K, true, HB, HASJ>), grid, dim3(threads), lds, s, a);
     else hipLaunchKernelGGL((k_tile3d<K, false, HB, HASJ>), grid, dim3(threads), lds, s, a);
