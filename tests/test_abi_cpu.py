@@ -171,3 +171,36 @@ def test_pa_tune_argument_errors(ctx):
     assert mcs._lib.mc_tune_pa(ctx, ctypes.byref(a0), ptrs, ws, 1 << 30, None, None) == mcs.MC_E_RANGE
     G = ctypes.c_int32()
     assert mcs._lib.mc_get_pa_group(ctx, 16, ctypes.byref(G)) == 0 and G.value == 16  # nothing was set
+
+
+def _plan(ctx, g):
+    H, K, T = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert mcs._lib.mc_get_tile_plan(ctx, ctypes.byref(g), ctypes.byref(H), ctypes.byref(K), ctypes.byref(T)) == 0
+    return H.value, K.value, T.value
+
+
+def test_tile_plans_default_set_and_limits(ctx):
+    """Launch shapes of the fused sweeps (host logic only): the built-in plans,
+    set/get per geometry, and the limits a plan must meet (threads a multiple
+    of 64 up to 1024; 2D: K <= 8, (H + 4K) rows x 2 Lx/64 words of LDS <= 64 KB;
+    3D: K <= 4, H <= min(Ly, Lz), the tile with couplings <= 96 KB)."""
+    g2 = mcs.make_geom(2, 4096, count=3)
+    g3 = mcs.make_geom(3, 256)
+    # 2D: 256 bands over the three lattices -> H = 4096 // 85 = 48, two sweeps
+    # per launch, (48 + 4) rows x 64 words of tasks -> 1024 threads
+    assert _plan(ctx, g2) == (48, 2, 1024)
+    # 3D: 16 x 16 tiles (one per CU at 256^3), two sweeps, 1024 threads
+    assert _plan(ctx, g3) == (16, 2, 1024)
+    set_ = lambda g, H, K, T: mcs._lib.mc_set_tile_plan(ctx, ctypes.byref(g), H, K, T)
+    assert set_(g2, 16, 4, 512) == 0
+    assert _plan(ctx, g2) == (16, 4, 512)
+    assert _plan(ctx, mcs.make_geom(2, 4096, count=2)) != (16, 4, 512)  # keyed by count too
+    for H, K, T in [(16, 4, 96), (16, 4, 32), (16, 4, 2048), (16, 9, 512), (0, 2, 512), (16, 0, 512),
+                    (200, 8, 1024)]:  # the last: (200 + 32) x 128 words x 4 B = 116 KB of LDS
+        assert set_(g2, H, K, T) == mcs.MC_E_RANGE, (H, K, T)
+    assert _plan(ctx, g2) == (16, 4, 512)  # a rejected plan leaves the set one
+    for H, K, T in [(16, 5, 1024), (257, 1, 1024), (32, 4, 1024)]:  # the last: 48^2 x 8 words x 4 B > 96 KB
+        assert set_(g3, H, K, T) == mcs.MC_E_RANGE, (H, K, T)
+    assert set_(g3, 8, 4, 256) == 0 and _plan(ctx, g3) == (8, 4, 256)
+    bad = mcs.Geom(2, 5, 8, 1, mcs.INT8, 1)
+    assert set_(bad, 4, 1, 64) == mcs.MC_E_SHAPE
