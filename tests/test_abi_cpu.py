@@ -204,3 +204,21 @@ def test_tile_plans_default_set_and_limits(ctx):
     assert set_(g3, 8, 4, 256) == 0 and _plan(ctx, g3) == (8, 4, 256)
     bad = mcs.Geom(2, 5, 8, 1, mcs.INT8, 1)
     assert set_(bad, 4, 1, 64) == mcs.MC_E_SHAPE
+
+
+@pytest.mark.parametrize("dims,L,layout,count", [
+    (2, (4096, 4096), mcs.INT8, 3), (3, (256, 256, 256), mcs.INT8, 1), (2, (128, 64), mcs.INT8, 1),
+    (2, (16384, 8), mcs.INT8, 1), (3, (64, 4, 8), mcs.INT8, 2), (3, (4096, 4, 4), mcs.INT8, 1),
+    (2, (96, 96), mcs.INT8, 1), (2, (4096, 4096), mcs.MSC64, 1), (3, (8192, 8, 8), mcs.INT8, 1),
+    (2, (32768, 4), mcs.INT8, 1), (3, (64, 2, 8), mcs.INT8, 1)])
+def test_sweep_workspace_bytes_follow_the_header(dims, L, layout, count):
+    """Two packed copies of the lattices (count N / 8 bytes each) and, in 3D,
+    three packed coupling planes (N / 8 each); zero where no fused kernel
+    applies (MSC64, Lx not a multiple of 64, 2D Lx > 16384, 3D Lx > 4096 or
+    Ly, Lz < 4)."""
+    g = mcs.make_geom(dims, L, layout=layout, count=count)
+    N = L[0] * L[1] * (L[2] if dims == 3 else 1)
+    fused = layout == mcs.INT8 and L[0] % 64 == 0 and (
+        L[0] <= 16384 if dims == 2 else (L[0] <= 4096 and min(L[1], L[2]) >= 4))
+    expect = (2 * count * N // 8 + (3 * N // 8 if dims == 3 else 0)) if fused else 0
+    assert mcs._lib.mc_sweep_workspace_bytes(ctypes.byref(g)) == expect
