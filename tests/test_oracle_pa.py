@@ -91,3 +91,27 @@ def test_lnZ_vs_kaufman_and_histogram_vs_exact():
     uex = float((pex * (4 * np.arange(N + 1) - 2 * N)).sum()) / N
     u = np.array([(p.hist[-1] * (4 * np.arange(N + 1) - 2 * N)).sum() / R / N for p in runs])
     assert abs(u.mean() - uex) < max(5 * u.std(ddof=1) / 2, 2e-3), (u.mean(), uex)
+
+
+@pytest.mark.parametrize("dbeta", [0.05, 0.3])
+def test_resampling_step_against_unshifted_weights(dbeta):
+    """One step without sweeps from a population of varied energies: the copy
+    numbers equal those of multinomial resampling written directly from the
+    reweighting factors exp(-dbeta E_j) (no shift, numpy's cumulative sum and
+    binary search), with the same uniform draws u_k; C_tot relates to the
+    unshifted sum by the factor exp(-2N dbeta), and ln Q to the mean factor."""
+    L, R, seed = 8, 400, 31
+    N = L * L
+    pop = oracle.PAPopulation(L, R, 0, seed)
+    E0 = pop.E.copy()
+    assert len(set(E0.tolist())) > 5  # hot starts: many energy levels
+    pop.advance(np.array([0.0, dbeta]), 0, 1)
+    w = np.exp(-dbeta * E0.astype(np.float64))
+    c = np.cumsum(w)
+    u = np.array([oracle.resample_u(seed, k, 0, 1) for k in range(R)])
+    parents = np.searchsorted(c, u * c[-1], side="right")
+    assert np.array_equal(pop.last_counts, np.bincount(parents, minlength=R))
+    assert abs(pop.Ctot[0] - c[-1] * math.exp(-2 * N * dbeta)) <= 1e-12 * c[-1] * math.exp(-2 * N * dbeta)
+    assert abs(pop.lnQ[0] - math.log(w.mean())) <= 1e-12
+    # the new population holds the copies in parent order
+    assert np.array_equal(pop.E, E0[np.sort(parents)])
