@@ -6,7 +6,15 @@
   with mean ~ 0 and variance a^2/3; biases start at zero;
 * the first Adam step moves every parameter with non-zero gradient by lr
   against the sign of its gradient (bias-corrected moments: m^/sqrt(v^) = sign);
-* training on the exact entropy deficit of small lattices lowers the loss.
+* training on the exact entropy deficit of small lattices lowers the loss;
+* what the network gains over the method without it, at sizes the CPU
+  handles: trained on the weights the plain recursion converges to at
+  L = 4, 8, 12, its initial ln W at L = 16 and 24 lies within a few units of
+  the exact -ln g (up to a constant), where the flat start is off by the whole
+  range of ln g; and the first recorded iteration of walkers prepared at the
+  learned weights visits every window level, where the flat start's visits
+  only the levels near E = 0.  (The sweeps-to-flat comparison itself runs at
+  L = 64, 96, 128 on the GPU.)
 """
 import math
 
@@ -80,3 +88,43 @@ def test_training_on_exact_entropy_lowers_loss():
     X, Y = mlp.training_set(lnW)
     p, losses = mlp.train(mlp.init_params(5), X, Y, 300, lr=3e-3)
     assert losses[-1] < 0.05 * losses[0]
+
+
+def test_learned_start_gains_over_flat_start():
+    # converged weights of the plain recursion (ln W = -ln g_est of a short
+    # production run) at the training sizes
+    lnW = {}
+    for L, rec_max in ((4, 10), (8, 40), (12, 40)):
+        r = oracle.muca_run(L, 512, 19 + L, eq_sweeps=2, rec_sweeps=10, max_iter=2000, prod_sweeps=400,
+                            rec_max=rec_max, prep_sweeps=400, rec_rule=1)
+        assert r["converged"], L
+        w = -np.where(np.isfinite(r["lng"]), r["lng"], 0.0)
+        lnW[L] = w - w[-1]
+    X, Y = mlp.training_set(lnW)
+    p, losses = mlp.train(mlp.init_params(1), X, Y, 3000)
+    assert losses[-1] < 1e-3 * losses[0]
+
+    def spread(L, w):
+        # max |ln W + ln g - c| over the reachable levels, best constant c
+        K = oracle.muca_levels(L)
+        g = exact.exact_g(L)
+        reach = oracle.muca_flat_levels(L)
+        d = np.array([exact.big_log(g[k]) + w[k] for k in range(K) if reach[k]])
+        return (d.max() - d.min()) / 2
+
+    for L, bound in ((16, 4.0), (24, 12.0)):
+        K = oracle.muca_levels(L)
+        learned, flat = spread(L, mlp.predict_lnW(p, L)), spread(L, np.zeros(K))
+        assert learned < bound and learned < flat / 20, (L, learned, flat)
+
+    L, W, seed = 16, 256, 201
+    K = oracle.muca_levels(L)
+    reach = oracle.muca_flat_levels(L)
+    coverage = {}
+    for arm, w in (("flat", np.zeros(K)), ("learned", mlp.predict_lnW(p, L))):
+        spins, E = oracle.muca_start(L, W, seed)
+        oracle.muca_prepare(L, spins, E, seed, w, 200)
+        oracle.muca_sweeps(L, spins, E, w, seed, 0, 2, False)
+        H = oracle.muca_sweeps(L, spins, E, w, seed, 2, 10, True)
+        coverage[arm] = float(np.mean(H[reach] > 0))
+    assert coverage["learned"] == 1.0 and coverage["flat"] < 0.3, coverage
