@@ -185,7 +185,6 @@ __global__ void k_phase_int8(SweepCall c, int8_t *spins, uint32_t sweep_lo, uint
     int8_t *s = spins + (int64_t)l * g.N;
     const uint32_t rep = c.replica0 + (uint32_t)l;
     const uint4 blk = philox(make_uint4((uint32_t)t16, rep, sweep_lo, w3), c.seed_lo, c.seed_hi);
-    const int z = 2 * g.dims;
     for (int k = 0; k < 16 && j0 + k < half; ++k) {
         const int64_t j = j0 + k;
         const Coord q = coord_of(g, j, phase);

@@ -104,8 +104,8 @@ int mc_mlp_train(mc_ctx *ctx, const mc_mlp_args *a, const float *X, const float 
         if (r == hipSuccess) r = ec;
         if (r == hipSuccess) r = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         for (int t = 0; t < times && r == hipSuccess; ++t) r = hipGraphLaunch(exec, s);
-        if (exec) hipGraphExecDestroy(exec);
-        if (graph) hipGraphDestroy(graph);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
         return r;
     };
     const int full = a->epochs / kChunk, rest = a->epochs % kChunk;

@@ -239,8 +239,8 @@ int mc_pa_anneal(mc_ctx *ctx, const mc_pa_args *a, void *const *pop_spins, doubl
                                hipMemcpyDeviceToHost, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return device_check(ctx, e, "mc_pa_anneal");
 
     // ln Q_i = log(C_total / R) + 2N dbeta_i;  ln Z_i = ln Z_{i-1} + ln Q_i,

@@ -243,9 +243,11 @@ int mc_tune_sweep_rule(mc_ctx *ctx, const mc_geom *geom, int32_t rule, void *scr
         return fail(ctx, MC_E_LAYOUT, "no tunable kernel for this geometry and rule");
     if ((rc = set_device(ctx))) return rc;
     hipStream_t s = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
         return fail(ctx, MC_E_DEVICE, "hipEventCreate failed");
+    }
     auto launch = [&](const void *src, int inp, void *dst, int outp, uint64_t sweep0, int K, const TilePlan &p,
                       int64_t *em) {
         return three ? launch_tile3d(c, src, inp, dst, outp, nullptr, sweep0, K, p.H, p.threads, em, 2 * g.count, 0, s)
@@ -289,14 +291,14 @@ int mc_tune_sweep_rule(mc_ctx *ctx, const mc_geom *geom, int32_t rule, void *scr
                 e = launch(scratch_b, 1, scratch_a, 1, 0, K, p, em);
                 float ms = 1e30f;
                 for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
-                    hipEventRecord(e0, s);
+                    e = hipEventRecord(e0, s);
                     for (int i = 0; i < n / K && e == hipSuccess; ++i)
                         e = launch((i & 1) ? scratch_b : scratch_a, 1, (i & 1) ? scratch_a : scratch_b, 1,
                                    (uint64_t)i * K, K, p, em);
-                    hipEventRecord(e1, s);
+                    if (e == hipSuccess) e = hipEventRecord(e1, s);
                     if (e == hipSuccess) e = hipEventSynchronize(e1);
                     float t = 0;
-                    if (e == hipSuccess) hipEventElapsedTime(&t, e0, e1);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
                     ms = std::min(ms, t / (float)n);
                 }
                 if (e != hipSuccess) break;
@@ -306,8 +308,8 @@ int mc_tune_sweep_rule(mc_ctx *ctx, const mc_geom *geom, int32_t rule, void *scr
                 }
             }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (e != hipSuccess) return device_check(ctx, e, "mc_tune_sweep");
     ctx->tile_plans[plan_key(g)] = best;
     return MC_OK;
