@@ -248,7 +248,11 @@ int mc_get_pa_group(mc_ctx *ctx, int32_t L, int32_t *G);
  * each, and keeps the fastest G in the context.  G_out: host [npop] or NULL.
  * pop_spins[p] and ws are scratch (contents overwritten); ws must hold
  * mc_pa_workspace_bytes of one population over those steps.  Synchronises
- * `stream`.                                                               */
+ * `stream`.  Errors (before any device work): those of mc_pa_anneal's
+ * arguments; MC_E_INVAL if an extent appears twice or pop_spins is NULL;
+ * MC_E_RANGE if the schedule has no step; MC_E_WORKSPACE if ws is too small.
+ * A device error while timing leaves the populations tuned so far set and
+ * the current one at its previous setting.                                */
 int mc_tune_pa(mc_ctx *ctx, const mc_pa_args *args, void *const *pop_spins, void *ws, size_t ws_bytes,
                int32_t *G_out, void *stream);
 

@@ -297,18 +297,27 @@ int mc_tune_pa(mc_ctx *ctx, const mc_pa_args *a, void *const *pop_spins, void *w
             if (a->L[q] == a->L[p]) return fail(ctx, MC_E_INVAL, "L=%d appears twice", a->L[p]);
     }
     // each population alone, over the first steps of the schedule, from a
-    // fresh start: every candidate runs identical work
+    // fresh start: every candidate runs identical work.  Every argument is
+    // checked before the first timed run.
     const int nst = std::min(a->step_first - 1 + a->nsteps, 20);
     if (nst < 1) return fail(ctx, MC_E_RANGE, "the schedule has no step to time");
+    std::vector<int32_t> Lone(a->npop);
+    std::vector<mc_pa_args> one(a->npop, *a);
+    for (int p = 0; p < a->npop; ++p) {
+        Lone[p] = a->L[p];
+        one[p].npop = 1;
+        one[p].L = &Lone[p];
+        one[p].step_first = 1;
+        one[p].nsteps = nst;
+        if (ws_bytes < mc_pa_workspace_bytes(&one[p]))
+            return fail(ctx, MC_E_WORKSPACE, "workspace too small for L=%d", a->L[p]);
+    }
+    if (!ws) return fail(ctx, MC_E_WORKSPACE, "workspace is NULL");
     for (int p = 0; p < a->npop; ++p) {
         const int L = a->L[p];
-        const int32_t Lp[1] = {L};
-        mc_pa_args b = *a;
-        b.npop = 1;
-        b.L = Lp;
-        b.step_first = 1;
-        b.nsteps = nst;
-        if (ws_bytes < mc_pa_workspace_bytes(&b)) return fail(ctx, MC_E_WORKSPACE, "workspace too small for L=%d", L);
+        const mc_pa_args &b = one[p];
+        const auto had = ctx->pa_groups.find(L);
+        const int G_prev = had != ctx->pa_groups.end() ? had->second : 0;
         const size_t N = (size_t)L * L;
         std::vector<double> C(nst), q(nst), z(nst + 1);
         std::vector<int64_t> h((size_t)(nst + 1) * (N + 1));
@@ -325,7 +334,8 @@ int mc_tune_pa(mc_ctx *ctx, const mc_pa_args *a, void *const *pop_spins, void *w
                 rc = mc_pa_anneal(ctx, &b, pop_spins + p, C.data(), q.data(), z.data(), h.data(), ws, ws_bytes, stream);
                 const auto t1 = std::chrono::steady_clock::now();
                 if (rc) {
-                    ctx->pa_groups.erase(L);
+                    if (G_prev) ctx->pa_groups[L] = G_prev;
+                    else ctx->pa_groups.erase(L);
                     return rc;
                 }
                 t = std::min(t, std::chrono::duration<double>(t1 - t0).count());

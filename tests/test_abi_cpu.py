@@ -166,6 +166,15 @@ def test_pa_tune_argument_errors(ctx):
     assert mcs._lib.mc_tune_pa(ctx, ctypes.byref(a), None, ws, 1 << 30, None, None) == mcs.MC_E_INVAL
     # workspace too small
     assert mcs._lib.mc_tune_pa(ctx, ctypes.byref(a), ptrs, ws, 16, None, None) == mcs.MC_E_WORKSPACE
+    # a NULL workspace of a claimed size
+    assert mcs._lib.mc_tune_pa(ctx, ctypes.byref(a), ptrs, None, 1 << 30, None, None) == mcs.MC_E_WORKSPACE
+    # the workspace fits the first population's timing run but not the second's:
+    # rejected before any run
+    a1 = mcs.PAArgs(1, Ls, 64, 1, 1, 1, 2, beta)
+    need16 = mcs._lib.mc_pa_workspace_bytes(ctypes.byref(a1))
+    assert 0 < need16
+    assert mcs._lib.mc_tune_pa(ctx, ctypes.byref(a), ptrs, ws, need16, None, None) == mcs.MC_E_WORKSPACE
+    assert b"L=32" in mcs._lib.mc_ctx_last_error(ctx)
     # no step to time
     a0 = mcs.PAArgs(2, Ls, 64, 1, 1, 1, 0, beta)
     assert mcs._lib.mc_tune_pa(ctx, ctypes.byref(a0), ptrs, ws, 1 << 30, None, None) == mcs.MC_E_RANGE
