@@ -69,7 +69,8 @@ typedef enum {
     MC_E_LAYOUT = -4,    /* layout / rule / coupling combination not supported     */
     MC_E_WORKSPACE = -5, /* workspace missing or smaller than required             */
     MC_E_DEVICE = -6,    /* HIP runtime error (detail in mc_ctx_last_error)        */
-    MC_E_NOTCONV = -7    /* multicanonical run hit max_iter (outputs still valid)  */
+    MC_E_NOTCONV = -7,   /* multicanonical run hit max_iter (outputs still valid)  */
+    MC_E_IO = -8         /* a file could not be opened, read or written            */
 } mc_status;
 
 enum { MC_INT8 = 0, MC_MSC64 = 1 };
@@ -255,6 +256,26 @@ int mc_get_pa_group(mc_ctx *ctx, int32_t L, int32_t *G);
  * the current one at its previous setting.                                */
 int mc_tune_pa(mc_ctx *ctx, const mc_pa_args *args, void *const *pop_spins, void *ws, size_t ws_bytes,
                int32_t *G_out, void *stream);
+
+/* Launch-shape cache: the tile plans (mc_set_tile_plan) and population-
+ * annealing groups (mc_set_pa_group) a context holds, tuned or set, saved to
+ * a text file and loaded into another context, so that tuning outlives the
+ * process.  Shapes change speed only, never results; a file belongs to one
+ * kind of device (tuned shapes are that device's).  Host only: no device
+ * work, no stream.
+ * Format: the line "libmcspin-launch-shapes 1", then one entry per line,
+ *   "tile dims Lx Ly Lz count H K threads" (Lz = 1 in 2D) or "pa L G";
+ *   '#' starts a comment, blank lines are skipped.
+ * mc_tuning_save writes path + ".tmp" and renames it to path.  MC_E_IO if
+ *   the file cannot be written; MC_E_INVAL for a NULL or empty path.
+ * mc_tuning_load checks every entry as the setters do, then applies them all
+ *   (overriding the context's entries for the same keys), or, on any error,
+ *   none: MC_E_IO if the file cannot be read; MC_E_INVAL for a missing
+ *   header, an unknown entry or a line over 255 characters; the setter's code
+ *   (MC_E_RANGE, MC_E_SHAPE) for an entry it rejects.  mc_ctx_last_error
+ *   names the file and line.                                             */
+int mc_tuning_save(mc_ctx *ctx, const char *path);
+int mc_tuning_load(mc_ctx *ctx, const char *path);
 
 /* ------------------------------------------------------------------------
  * Multicanonical simulation with parallel walkers (Sec. "Multicanonical

@@ -21,8 +21,8 @@ METROPOLIS, HEATBATH = 0, 1
 COLD, HOT = 0, 1
 MUCA_HOT, MUCA_STRATIFIED = 0, 1
 
-MC_OK, MC_E_INVAL, MC_E_SHAPE, MC_E_RANGE, MC_E_LAYOUT, MC_E_WORKSPACE, MC_E_DEVICE, MC_E_NOTCONV = \
-    0, -1, -2, -3, -4, -5, -6, -7
+MC_OK, MC_E_INVAL, MC_E_SHAPE, MC_E_RANGE, MC_E_LAYOUT, MC_E_WORKSPACE, MC_E_DEVICE, MC_E_NOTCONV, MC_E_IO = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
 
 
 class MCError(RuntimeError):
@@ -142,6 +142,8 @@ _lib_fns = dict(
                                                  _c.POINTER(_c.c_double), _c.POINTER(_c.c_double),
                                                  _c.POINTER(_c.c_int64), _vp, _c.c_size_t, _vp]),
     mc_set_pa_group=_sig("mc_set_pa_group", _c.c_int, [_vp, _c.c_int32, _c.c_int32]),
+    mc_tuning_save=_sig("mc_tuning_save", _c.c_int, [_vp, _c.c_char_p]),
+    mc_tuning_load=_sig("mc_tuning_load", _c.c_int, [_vp, _c.c_char_p]),
     mc_get_pa_group=_sig("mc_get_pa_group", _c.c_int, [_vp, _c.c_int32, _c.POINTER(_c.c_int32)]),
     mc_tune_pa=_sig("mc_tune_pa", _c.c_int, [_vp, _c.POINTER(PAArgs), _c.POINTER(_vp), _vp, _c.c_size_t,
                                              _c.POINTER(_c.c_int32), _vp]),
@@ -303,6 +305,14 @@ class Context:
     def set_pa_group(self, L, G):
         """Replicas per workgroup for populations of extent L (0: built-in rule)."""
         return self._check(_lib.mc_set_pa_group(self._h, L, G), "mc_set_pa_group")
+
+    def save_launch_shapes(self, path):
+        """Write the context's tile plans and PA groups to a text file."""
+        return self._check(_lib.mc_tuning_save(self._h, os.fsencode(path)), "mc_tuning_save")
+
+    def load_launch_shapes(self, path):
+        """Read launch shapes written by save_launch_shapes (all or none)."""
+        return self._check(_lib.mc_tuning_load(self._h, os.fsencode(path)), "mc_tuning_load")
 
     def get_pa_group(self, L):
         G = ctypes.c_int32()

@@ -126,6 +126,7 @@ const char *mc_strerror(int code)
     case MC_E_WORKSPACE: return "workspace missing or too small";
     case MC_E_DEVICE: return "HIP device error";
     case MC_E_NOTCONV: return "multicanonical iteration did not converge";
+    case MC_E_IO: return "file could not be opened, read or written";
     default: return "unknown error code";
     }
 }
