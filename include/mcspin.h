@@ -78,7 +78,8 @@ enum { MC_METROPOLIS = 0, MC_HEATBATH = 1 };
 enum { MC_COLD = 0, MC_HOT = 1 };
 
 /* dims = 2 or 3; Lz = 1 when dims == 2; count = number of int8 lattices or of
- * 64-lane word lattices.  Every extent must be even and >= 4.              */
+ * 64-lane word lattices, 1..65535 (MC_E_RANGE otherwise).  Every extent must
+ * be even and >= 4.                                                        */
 typedef struct {
     int32_t dims, Lx, Ly, Lz, layout, count;
 } mc_geom;
@@ -339,7 +340,8 @@ typedef struct {
                              inverse temperature -d lnW/dE (central difference
                              around level round((g + 1/2) N / 32), at least 0;
                              flat weights: 0); energies are then recomputed and
-                             walkers above the window flipped (E -> -E)       */
+                             walkers above the window flipped (E -> -E);
+                             needs walkers <= 16 * 65535                      */
     int32_t rec_rule;     /* 0: double the recorded sweeps after every
                              iteration that reached every window level; 1:
                              only when such an iteration's flatness did not

@@ -71,6 +71,8 @@ int check_geom(mc_ctx *ctx, const mc_geom *g, bool need_count)
     const double N = (double)g->Lx * g->Ly * Lz;
     if (N > 4294967296.0) return fail(ctx, MC_E_SHAPE, "more than 2^32 sites per lattice");
     if (need_count && (g->count < 1)) return fail(ctx, MC_E_RANGE, "count must be >= 1 (got %d)", g->count);
+    // the lattice index is a launch dimension of at most 65535 workgroups
+    if (need_count && g->count > 65535) return fail(ctx, MC_E_RANGE, "count must be <= 65535 (got %d)", g->count);
     if (need_count && (double)g->count * N * (g->layout == MC_MSC64 ? 8.0 : 1.0) > 1.0e12)
         return fail(ctx, MC_E_RANGE, "lattice buffer too large");
     // replica ids must fit 32 bits (checked by the callers that know replica0)

@@ -187,6 +187,9 @@ int mc_muca_run(mc_ctx *ctx, const mc_muca_args *a, const double *lnW_init, int8
     if (a->eq_scale < 0 || a->eq_scale > 64) return fail(ctx, MC_E_RANGE, "eq_scale out of range");
     if (a->prep_sweeps < 0 || a->rec_rule < 0 || a->rec_rule > 1)
         return fail(ctx, MC_E_RANGE, "prep_sweeps or rec_rule out of range");
+    // each preparation group is one sweep call of up to 65535 lattices
+    if (a->prep_sweeps > 0 && (a->walkers + kPrepGroups - 1) / kPrepGroups > 65535)
+        return fail(ctx, MC_E_RANGE, "prep_sweeps needs walkers <= %d", kPrepGroups * 65535);
     const int L = a->L, W = a->walkers, K = L * L / 2;
     const MucaLayout lay = muca_layout(L, W);
     if (!ws || ws_bytes < lay.total) return fail(ctx, MC_E_WORKSPACE, "workspace needs %zu bytes", lay.total);

@@ -91,6 +91,10 @@ def test_other_argument_errors(ctx):
     assert _sweep(ctx, bad_layout, mcs.SweepArgs(0, 0.4, 1, 0, 0, 1)) == mcs.MC_E_INVAL
     zero = mcs.Geom(2, 8, 8, 1, mcs.INT8, 0)
     assert _sweep(ctx, zero, mcs.SweepArgs(0, 0.4, 1, 0, 0, 1)) == mcs.MC_E_RANGE
+    many = mcs.Geom(2, 8, 8, 1, mcs.INT8, 65536)  # one launch dimension per lattice: at most 65535
+    assert _sweep(ctx, many, mcs.SweepArgs(0, 0.4, 1, 0, 0, 1)) == mcs.MC_E_RANGE
+    assert mcs._lib.mc_init(ctx, ctypes.byref(many), FAKE, 1, 1, 0, None) == mcs.MC_E_RANGE
+    assert mcs._lib.mc_measure(ctx, ctypes.byref(many), FAKE, None, FAKE, None) == mcs.MC_E_RANGE
     assert mcs._lib.mc_init(ctx, ctypes.byref(g), FAKE, 2, 1, 0, None) == mcs.MC_E_INVAL
     assert mcs._lib.mc_init(ctx, ctypes.byref(g), None, 1, 1, 0, None) == mcs.MC_E_INVAL
     assert mcs._lib.mc_measure(ctx, ctypes.byref(g), FAKE, None, None, None) == mcs.MC_E_INVAL
@@ -231,3 +235,22 @@ def test_sweep_workspace_bytes_follow_the_header(dims, L, layout, count):
         L[0] <= 16384 if dims == 2 else (L[0] <= 4096 and min(L[1], L[2]) >= 4))
     expect = (2 * count * N // 8 + (3 * N // 8 if dims == 3 else 0)) if fused else 0
     assert mcs._lib.mc_sweep_workspace_bytes(ctypes.byref(g)) == expect
+
+
+def test_muca_preparation_walker_limit(ctx):
+    """Walker preparation sweeps run per group of walkers / 16 lattices, one
+    launch dimension of at most 65535 lattices: more walkers are rejected up
+    front; the same count without preparation passes this check (and fails
+    only at the NULL workspace)."""
+    dp = ctypes.cast(FAKE, ctypes.POINTER(ctypes.c_double))
+    ip = ctypes.cast(FAKE, ctypes.POINTER(ctypes.c_int64))
+    st = mcs.MucaStats()
+
+    def run(walkers, prep):
+        a = mcs.MucaArgs(8, walkers, 2, 10, 10, 0, 0.8, 1, mcs.MUCA_HOT, 0, 0, prep, 0, mcs.PROGRESS_FN(), None)
+        return mcs._lib.mc_muca_run(ctx, ctypes.byref(a), None, FAKE, dp, ip, dp, dp, ctypes.byref(st), None, 0, None)
+
+    assert run(16 * 65535 + 1, 1) == mcs.MC_E_RANGE
+    assert b"walkers" in mcs._lib.mc_ctx_last_error(ctx)
+    assert run(16 * 65535 + 1, 0) == mcs.MC_E_WORKSPACE
+    assert run(16 * 65535, 1) == mcs.MC_E_WORKSPACE
