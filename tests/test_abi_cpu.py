@@ -254,3 +254,20 @@ def test_muca_preparation_walker_limit(ctx):
     assert b"walkers" in mcs._lib.mc_ctx_last_error(ctx)
     assert run(16 * 65535 + 1, 0) == mcs.MC_E_WORKSPACE
     assert run(16 * 65535, 1) == mcs.MC_E_WORKSPACE
+
+
+def test_import_fails_loudly_without_the_library(tmp_path):
+    """A copy of the package without libmcspin.so must refuse to import: there
+    is no fallback path."""
+    import shutil
+    import subprocess
+    import sys
+
+    pkg = tmp_path / "paper_1709_04394_amd"
+    pkg.mkdir()
+    for name in ("__init__.py", "learned_muca.py"):
+        shutil.copy(os.path.join(ROOT, "paper_1709_04394_amd", name), pkg / name)
+    code = "import paper_1709_04394_amd"
+    r = subprocess.run([sys.executable, "-c", code], cwd=str(tmp_path), capture_output=True, text=True, timeout=300,
+                       env=dict(os.environ, PYTHONPATH=str(tmp_path)))
+    assert r.returncode != 0 and "ImportError" in r.stderr and "libmcspin.so is not built" in r.stderr, r.stderr
