@@ -208,3 +208,29 @@ def test_prepare_gives_canonical_walkers():
     assert np.all(E <= 0)
     u, _ = exact.kaufman_u_cv(L, beta0)
     assert abs(E.mean() / N - u) < 0.04, (E.mean() / N, u)
+
+
+def test_settle_folds_walkers_into_the_window():
+    """Every bond joins the two sub-lattices, so flipping the odd one maps E to
+    -E: a walker above the window is folded into it (the antiferromagnet,
+    E = +2N, becomes the ground state, E = -2N), a walker inside is left
+    alone, and the stored energies are those of the returned lattices."""
+    L, W = 6, 6
+    N = L * L
+    x, y = np.meshgrid(np.arange(L), np.arange(L))
+    af = np.where((x + y) % 2 == 0, 1, -1).astype(np.int8).reshape(-1)
+    rows = [np.ones(N, dtype=np.int8), af, -af] + [oracle.init(2, L, oracle.HOT, 5, r) for r in range(3)]
+    spins = np.concatenate(rows).astype(np.int8)
+    before = spins.reshape(W, N).copy()
+    E = np.zeros(W, dtype=np.int64)
+    assert oracle.lib().orc_muca_settle(L, W, oracle._p(spins), oracle._p(E)) == 0
+    odd = ((x + y) % 2 == 1).reshape(-1)
+    for w in range(W):
+        e0 = oracle.measure(2, L, before[w])[0]
+        s = spins.reshape(W, N)[w]
+        assert E[w] == oracle.measure(2, L, s)[0] == -abs(e0)
+        want = before[w].copy()
+        if e0 > 0:
+            want[odd] = -want[odd]
+        assert np.array_equal(s, want)
+    assert E[1] == E[2] == -2 * N and np.all(spins.reshape(W, N)[1] == 1) and np.all(spins.reshape(W, N)[2] == -1)

@@ -133,3 +133,24 @@ def test_draws_follow_the_documented_counter_layout(seed, tag, replica, sweep, p
             lo = oracle.philox([j, replica, sweep & 0xFFFFFFFF, w3(oracle.TAG_SWEEP_LO)], key)
             r = oracle.draw32(seed, tag, oracle.TAG_SWEEP_LO, j, replica, sweep, phase)
             assert r == (_gather_byte(blk, j & 15) << 24) | (int(lo[0]) & 0xFFFFFF)
+
+
+@pytest.mark.parametrize("seed,pop,step", [(17, 2, 33), ((5 << 36) | 9, 0, 1), (1, 7, 200)])
+def test_resample_u_follows_the_documented_construction(seed, pop, step):
+    # u_k = ((w0 >> 5) 2^26 + (w1 >> 6)) 2^-53, w = Philox(ctr = (k, pop, step,
+    # TAG_RESAMPLE << 24)) under key (seed low word, seed high word)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for k in list(range(50)) + [4095, 65535]:
+        w = oracle.philox([k, pop, step, oracle.TAG_RESAMPLE << 24], key)
+        want = ((int(w[0]) >> 5) * 2 ** 26 + (int(w[1]) >> 6)) / 2.0 ** 53
+        assert oracle.resample_u(seed, k, pop, step) == want
+
+
+@pytest.mark.parametrize("seed,replica,sweep", [(99, 2, 7), ((3 << 33) | 1, 4095, (1 << 32) + 3)])
+def test_draw_word_follows_the_documented_construction(seed, replica, sweep):
+    # item j of a sequential chain: word (j mod 4) of Philox(ctr = (j div 4,
+    # replica, sweep low word, tag << 24 | sweep >> 32))
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for j in list(range(20)) + [16383]:
+        w = oracle.philox([j >> 2, replica, sweep & 0xFFFFFFFF, (oracle.TAG_MUCA << 24) | (sweep >> 32)], key)
+        assert oracle.draw_word(seed, oracle.TAG_MUCA, j, replica, sweep) == int(w[j & 3])
