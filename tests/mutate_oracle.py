@@ -3,13 +3,13 @@
 
     python tests/mutate_oracle.py [--jobs N] [--only NAME ...]
 
-Each mutant plants one plausible mistake in a temporary copy of
-oracle/mcoracle.c: a dropped term, a wrong sign, index, constant or bit
-order, a changed update order or stream number.  The copy is built and the
-CPU pin tests (tests/test_oracle_*.py but the sanitizer run, and
-tests/test_golden_lng.py) run
-against it; the mutant is caught when any of them fails.  The working tree is
-never modified.  One line per mutant is printed, then the count caught.
+Each mutant plants one plausible mistake in a temporary copy of the oracle
+(oracle/mcoracle.c, or oracle/mlp.py for the network): a dropped term, a
+wrong sign, index, constant or bit order, a changed update order or stream
+number.  The copy is built and the CPU pin tests (tests/test_oracle_*.py but
+the sanitizer run, and tests/test_golden_lng.py) run against it; the mutant
+is caught when any of them fails.  The working tree is never modified.  One
+line per mutant is printed, then the count caught.
 """
 import argparse
 import concurrent.futures as cf
@@ -22,7 +22,7 @@ import time
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-# (name, text in mcoracle.c (must occur once), replacement)
+# (name, text (must occur once), replacement[, file; default oracle/mcoracle.c])
 MUTANTS = [
     # Philox4x32-10 (Sec. "Random number generation")
     ("philox: key dropped from a round", "uint32_t y0 = hi1 ^ x1 ^ k0;", "uint32_t y0 = hi1 ^ x1;"),
@@ -92,6 +92,14 @@ MUTANTS = [
     ("muca: start threshold off by one", "(uint32_t)w, 0, 0) >= 256u - c ? -1 : 1;",
      "(uint32_t)w, 0, 0) > 256u - c ? -1 : 1;"),
     ("muca: settle keeps E above the window", "            e = -e;\n", "            e = e;\n"),
+    # the FP64 network (oracle/mlp.py)
+    ("mlp: second layer linear (forward and backward)",
+     "    h2 = np.tanh(z2)\n", "    h2 = z2\n", "oracle/mlp.py"),
+    ("mlp: first-layer gradient without tanh'", 'dz1 = (dz2 @ q["W2"]) * (1.0 - h1 * h1)',
+     'dz1 = (dz2 @ q["W2"])', "oracle/mlp.py"),
+    ("mlp: Adam without bias correction", "mh = m / (1.0 - beta1 ** t)", "mh = m", "oracle/mlp.py"),
+    ("mlp: Xavier bound sqrt(3 / fan)", "a = math.sqrt(6.0 / (fan_in + fan_out))",
+     "a = math.sqrt(3.0 / (fan_in + fan_out))", "oracle/mlp.py"),
 ]
 
 PIN_TESTS = ["tests/test_golden_lng.py", "tests/test_oracle_exact.py", "tests/test_oracle_mlp.py",
@@ -112,10 +120,11 @@ def _copy_tree(dst):
 
 
 def run_mutant(m):
-    name, old, new = m
+    name, old, new = m[:3]
+    rel = m[3] if len(m) > 3 else "oracle/mcoracle.c"
     with tempfile.TemporaryDirectory(prefix="mut_") as d:
         _copy_tree(d)
-        path = os.path.join(d, "oracle", "mcoracle.c")
+        path = os.path.join(d, rel)
         text = open(path).read()
         if text.count(old) != 1:
             return name, "not applicable (pattern found %d times)" % text.count(old), 0.0

@@ -128,3 +128,40 @@ def test_learned_start_gains_over_flat_start():
         H = oracle.muca_sweeps(L, spins, E, w, seed, 2, 10, True)
         coverage[arm] = float(np.mean(H[reach] > 0))
     assert coverage["learned"] == 1.0 and coverage["flat"] < 0.3, coverage
+
+
+def test_forward_gradient_and_adam_match_torch_float64():
+    """The network, its MSE gradient and full-batch Adam against torch's own
+    modules in float64 on the CPU (an independent implementation of the same
+    definitions): 2 -> 64 tanh -> 64 tanh -> 1 with weights [out][in]."""
+    import torch
+
+    X, Y = _data(n=150, seed=4)
+    p0 = mlp.init_params(3) + 0.01 * np.random.default_rng(5).standard_normal(mlp.NPARAMS)
+    q = mlp.unflatten(p0)
+    net = torch.nn.Sequential(torch.nn.Linear(2, 64), torch.nn.Tanh(), torch.nn.Linear(64, 64), torch.nn.Tanh(),
+                              torch.nn.Linear(64, 1)).double()
+    with torch.no_grad():
+        for layer, (w, b) in zip((net[0], net[2], net[4]), (("W1", "b1"), ("W2", "b2"), ("W3", "b3"))):
+            layer.weight.copy_(torch.from_numpy(q[w]))
+            layer.bias.copy_(torch.from_numpy(q[b]))
+    Xt, Yt = torch.from_numpy(X), torch.from_numpy(Y)
+    y, _ = mlp.forward(p0, X)
+    assert np.allclose(y, net(Xt)[:, 0].detach().numpy(), rtol=1e-13, atol=1e-14)
+    loss_t = torch.mean((net(Xt)[:, 0] - Yt) ** 2)
+    loss_t.backward()
+    loss, g = mlp.loss_and_grad(p0, X, Y)
+    gt = np.concatenate([t.grad.numpy().reshape(-1) for t in (net[0].weight, net[0].bias, net[2].weight,
+                                                               net[2].bias, net[4].weight, net[4].bias)])
+    assert abs(loss - loss_t.item()) <= 1e-13 * loss_t.item()
+    assert np.allclose(g, gt, rtol=1e-10, atol=1e-14 * np.abs(gt).max())
+    # five Adam steps (lr, beta1, beta2, eps as the oracle's defaults)
+    opt = torch.optim.Adam(net.parameters(), lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    for _ in range(5):
+        opt.zero_grad()
+        torch.mean((net(Xt)[:, 0] - Yt) ** 2).backward()
+        opt.step()
+    p5, _ = mlp.train(p0, X, Y, 5)
+    pt = np.concatenate([t.detach().numpy().reshape(-1) for t in (net[0].weight, net[0].bias, net[2].weight,
+                                                                   net[2].bias, net[4].weight, net[4].bias)])
+    assert np.allclose(p5, pt, rtol=1e-9, atol=1e-12)
