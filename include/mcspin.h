@@ -43,8 +43,9 @@
  * k / 2.  One block thus gives 16 bytes as eight bit-planes, the form the
  * bit-sliced kernels consume.  "Word 0" is w0.  The tags in counter word 3
  * (bits 24..31) are TAG_INIT = 1, TAG_SWEEP = 2, TAG_COUPLING = 3,
- * TAG_RESAMPLE = 4, TAG_MUCA = 5, TAG_MLP_INIT = 6, TAG_SWEEP_LO = 7 (8 is
- * reserved); bit 23 holds the half-sweep colour where one is given, bits
+ * TAG_RESAMPLE = 4, TAG_MUCA = 5, TAG_MLP_INIT = 6, TAG_SWEEP_LO = 7,
+ * TAG_EXCHANGE = 9 (8 is reserved); bit 23 holds the half-sweep colour where
+ * one is given, bits
  * 0..22 the high bits of a 64-bit sweep number.
  */
 #ifndef MCSPIN_H
@@ -257,6 +258,27 @@ int mc_get_pa_group(mc_ctx *ctx, int32_t L, int32_t *G);
  * the current one at its previous setting.                                */
 int mc_tune_pa(mc_ctx *ctx, const mc_pa_args *args, void *const *pop_spins, void *ws, size_t ws_bytes,
                int32_t *G_out, void *stream);
+
+/* Parallel tempering (Sec. "Parallel Tempering", Eq. pt): one round of
+ * replica-exchange moves, on the host.  n_temps replicas are held at the
+ * inverse temperatures beta[0] < beta[1] < ... (host, strictly increasing,
+ * finite, >= 0); replica_at[i] is the replica at temperature i and
+ * temp_of[a] the temperature of replica a (host int32 [n_temps], inverse
+ * permutations of 0..n_temps-1); E[a] is replica a's energy (host int64,
+ * |E| <= 2^52), e.g. the last row of the per-sweep E of mc_sweep_betas run
+ * with betas[a] = beta[temp_of[a]].  Round t proposes the pairs (i, i + 1)
+ * with i = t mod 2, t mod 2 + 2, ...; with a, b the replicas at i and i + 1 the
+ * exchange is accepted with min(1, exp((beta_i - beta_{i+1}) (E_a - E_b))):
+ * always if the exponent is >= 0, else iff r32 < ceil(exp(exponent) 2^32)
+ * (host FP64 libm exp), r32 = word (i mod 4) of Philox(ctr = (i / 4, 0, t,
+ * TAG_EXCHANGE << 24 | t >> 32)).  Accepted: the two replicas' temperatures
+ * are swapped in both maps and accepted[i] (host int64 [n_temps - 1]) is
+ * incremented.  Configurations never move.  Host only: no device work.
+ * Errors: MC_E_INVAL for a NULL pointer or maps that are not inverse
+ * permutations; MC_E_RANGE for n_temps outside 2..2^20, a beta out of range
+ * or not increasing, |E| > 2^52 or t >= 2^55.  Nothing is changed on error. */
+int mc_pt_exchange(mc_ctx *ctx, int32_t n_temps, const double *beta, const int64_t *E, int32_t *temp_of,
+                   int32_t *replica_at, uint64_t seed, uint64_t round, int64_t *accepted);
 
 /* Launch-shape cache: the tile plans (mc_set_tile_plan) and population-
  * annealing groups (mc_set_pa_group) a context holds, tuned or set, saved to

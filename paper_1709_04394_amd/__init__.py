@@ -142,6 +142,10 @@ _lib_fns = dict(
                                                  _c.POINTER(_c.c_double), _c.POINTER(_c.c_double),
                                                  _c.POINTER(_c.c_int64), _vp, _c.c_size_t, _vp]),
     mc_set_pa_group=_sig("mc_set_pa_group", _c.c_int, [_vp, _c.c_int32, _c.c_int32]),
+    mc_pt_exchange=_sig("mc_pt_exchange", _c.c_int, [_vp, _c.c_int32, _c.POINTER(_c.c_double),
+                                                     _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int32),
+                                                     _c.POINTER(_c.c_int32), _c.c_uint64, _c.c_uint64,
+                                                     _c.POINTER(_c.c_int64)]),
     mc_tuning_save=_sig("mc_tuning_save", _c.c_int, [_vp, _c.c_char_p]),
     mc_tuning_load=_sig("mc_tuning_load", _c.c_int, [_vp, _c.c_char_p]),
     mc_get_pa_group=_sig("mc_get_pa_group", _c.c_int, [_vp, _c.c_int32, _c.POINTER(_c.c_int32)]),
@@ -305,6 +309,25 @@ class Context:
     def set_pa_group(self, L, G):
         """Replicas per workgroup for populations of extent L (0: built-in rule)."""
         return self._check(_lib.mc_set_pa_group(self._h, L, G), "mc_set_pa_group")
+
+    def pt_exchange(self, beta, E, temp_of, replica_at, seed, round, accepted):
+        """One round of replica exchanges (mc_pt_exchange) on numpy arrays:
+        beta float64 [n], E int64 [n] by replica, temp_of / replica_at int32 [n]
+        and accepted int64 [n-1], the last three updated in place."""
+        import numpy as np
+
+        beta = np.ascontiguousarray(beta, dtype=np.float64)
+        E = np.ascontiguousarray(E, dtype=np.int64)
+        for a, dt in ((temp_of, np.int32), (replica_at, np.int32), (accepted, np.int64)):
+            if not (isinstance(a, np.ndarray) and a.dtype == dt and a.flags.c_contiguous):
+                raise TypeError("temp_of, replica_at: contiguous int32 arrays; accepted: contiguous int64")
+        n = beta.size
+        if E.size != n or temp_of.size != n or replica_at.size != n or accepted.size != max(n - 1, 0):
+            raise ValueError("beta, E, temp_of, replica_at need n entries and accepted n - 1")
+        p = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))
+        return self._check(_lib.mc_pt_exchange(self._h, n, p(beta, ctypes.c_double), p(E, ctypes.c_int64),
+                                               p(temp_of, ctypes.c_int32), p(replica_at, ctypes.c_int32), seed,
+                                               round, p(accepted, ctypes.c_int64)), "mc_pt_exchange")
 
     def save_launch_shapes(self, path):
         """Write the context's tile plans and PA groups to a text file."""

@@ -1,7 +1,7 @@
 """libmcspin's host code under AddressSanitizer and UndefinedBehaviorSanitizer
 (no GPU needed, no device work).  The host-side translation units (argument
 checks, tables, launch-shape settings, the launch-shape file parser, the
-training-set builder) are rebuilt with the sanitizers on the host pass only
+training-set builder, the replica-exchange step) are rebuilt with the sanitizers on the host pass only
 and linked with the kernel objects of the normal build; a C driver built
 with the same compiler family then calls every host-only entry point --
 valid and invalid arguments, a cache round trip and malformed cache files --
@@ -18,9 +18,10 @@ CSRC = os.path.join(ROOT, "paper_1709_04394_amd", "csrc")
 OBJS = os.path.join(ROOT, "paper_1709_04394_amd", "_build")
 HIPCC = "/opt/rocm/bin/hipcc"
 CLANG = "/opt/rocm/llvm/bin/clang"
-HOST_UNITS = ["abi", "tuning", "sweep_driver", "pa_driver", "muca_driver", "mlp_driver"]
+HOST_UNITS = ["abi", "tuning", "tempering", "sweep_driver", "pa_driver", "muca_driver", "mlp_driver"]
 
 DRIVER = r"""
+#include <stdint.h>
 #include <stdio.h>
 #include <string.h>
 #include "mcspin.h"
@@ -85,6 +86,16 @@ int main(int argc, char **argv)
     CHECK(mc_mlp_training_set(ctx, 2, tl, tw, X, Y, 64, &n) == MC_OK && n == 8 + 32);
     CHECK(mc_mlp_training_set(ctx, 2, tl, tw, X, Y, 10, &n) == MC_E_RANGE);
     CHECK(mc_mlp_param_count() == 4417 && mc_mlp_workspace_bytes(100) > 0);
+
+    /* parallel tempering exchange (host only) */
+    double tb[3] = {0.1, 0.2, 0.3};
+    int64_t tE[3] = {-8, 0, 4}, tacc[2] = {0, 0};
+    int32_t tof[3] = {0, 1, 2}, rat[3] = {0, 1, 2};
+    for (uint64_t t = 0; t < 100; ++t) CHECK(mc_pt_exchange(ctx, 3, tb, tE, tof, rat, 1, t, tacc) == MC_OK);
+    CHECK(rat[tof[0]] == 0 && rat[tof[1]] == 1 && rat[tof[2]] == 2);
+    CHECK(mc_pt_exchange(ctx, 3, tb, tE, tof, rat, 1, (uint64_t)1 << 55, tacc) == MC_E_RANGE);
+    tof[0] = tof[1];
+    CHECK(mc_pt_exchange(ctx, 3, tb, tE, tof, rat, 1, 0, tacc) == MC_E_INVAL);
 
     /* launch-shape file: round trip, then malformed files */
     CHECK(mc_tuning_save(ctx, argv[1]) == MC_OK);
