@@ -4,7 +4,7 @@
     python tests/mutate_oracle.py [--jobs N] [--only NAME ...]
 
 Each mutant plants one plausible mistake in a temporary copy of the oracle
-(oracle/mcoracle.c, or oracle/mlp.py for the network): a dropped term, a
+(oracle/mcoracle.c, oracle/mlp.py or oracle/__init__.py): a dropped term, a
 wrong sign, index, constant or bit order, a changed update order or stream
 number.  The copy is built and the CPU pin tests (tests/test_oracle_*.py but
 the sanitizer run, and tests/test_golden_lng.py) run against it; the mutant
@@ -100,11 +100,18 @@ MUTANTS = [
     ("mlp: Adam without bias correction", "mh = m / (1.0 - beta1 ** t)", "mh = m", "oracle/mlp.py"),
     ("mlp: Xavier bound sqrt(3 / fan)", "a = math.sqrt(6.0 / (fan_in + fan_out))",
      "a = math.sqrt(3.0 / (fan_in + fan_out))", "oracle/mlp.py"),
+    # parallel tempering (oracle/__init__.py, Sec. "Parallel Tempering", Eq. pt)
+    ("pt: exponent sign", "x = (beta[i] - beta[i + 1]) * float(E[a] - E[b])",
+     "x = (beta[i + 1] - beta[i]) * float(E[a] - E[b])", "oracle/__init__.py"),
+    ("pt: every pair every round", "for i in range(rnd % 2, nT - 1, 2):", "for i in range(0, nT - 1):",
+     "oracle/__init__.py"),
+    ("pt: one map not updated", "            temp_of[a], temp_of[b] = i + 1, i\n", "", "oracle/__init__.py"),
 ]
 
 PIN_TESTS = ["tests/test_golden_lng.py", "tests/test_oracle_exact.py", "tests/test_oracle_mlp.py",
-             "tests/test_oracle_muca.py", "tests/test_oracle_pa.py", "tests/test_oracle_rng.py",
-             "tests/test_oracle_streams.py", "tests/test_oracle_sweep.py", "tests/test_oracle_tables.py"]
+             "tests/test_oracle_muca.py", "tests/test_oracle_pa.py", "tests/test_oracle_pt.py",
+             "tests/test_oracle_rng.py", "tests/test_oracle_streams.py", "tests/test_oracle_sweep.py",
+             "tests/test_oracle_tables.py"]
 
 
 def _copy_tree(dst):
