@@ -6,8 +6,9 @@
  * leg of the benchmark may use it.  It shares no code, header or table
  * generator with the HIP library: every piece of arithmetic below is written
  * out again from the paper (M. Weigel, "Monte Carlo methods for massively
- * parallel computers", arXiv:1709.04394) and from the readings recorded in the
- * design notes, as plainly as possible, in the order the paper states it.
+ * parallel computers", arXiv:1709.04394), with the reading of the paper taken
+ * where it leaves a choice stated beside each routine, as plainly as possible,
+ * in the order the paper states it.
  *
  * Contents
  *   Philox4x32-10 ............ Sec. "Random number generation", counter-based
