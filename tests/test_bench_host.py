@@ -1,0 +1,33 @@
+"""Host logic of bench.py (no GPU): the committed counter summaries of the
+dominant kernel match its current source and the measured launch shape, so
+the benchmark line carries measured HBM traffic and VALU issue; a different
+launch shape or source is refused (null), never reported."""
+import importlib.util
+import os
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    return b
+
+
+def test_counter_summaries_match_the_kernel_source():
+    b = _bench()
+    plan = (16, 4, 512)  # the launch shape the summaries were taken with
+    traffic = b.measured_traffic(plan)
+    assert traffic is not None, "k_tile2d.hip changed since its counters were taken: profile it again"
+    # about 28.5 MB per launch, well below the 402.7 MB of algorithmic int8 bytes
+    assert 20e6 < traffic < 40e6
+    v = b.measured_valu(plan, 73.4e-6)
+    assert v is not None and 0.5 < v["frac"] < 1.0
+    assert b.VALU_PEAK_WAVE_INSTS == 256 * 4 * 2.4e9 / 4
+
+
+def test_other_launch_shapes_are_refused():
+    b = _bench()
+    assert b.measured_traffic((16, 2, 512)) is None
+    assert b.measured_valu((8, 4, 512), 73.4e-6) is None
