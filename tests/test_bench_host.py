@@ -31,3 +31,13 @@ def test_other_launch_shapes_are_refused():
     b = _bench()
     assert b.measured_traffic((16, 2, 512)) is None
     assert b.measured_valu((8, 4, 512), 73.4e-6) is None
+
+
+def test_cpu_baseline_leg_reports_all_cores_and_one_thread():
+    """The oracle leg of the benchmark runs on the host only; a short sample."""
+    b = _bench()
+    out = b.cpu_baseline(1.5)
+    assert out["kind"] == "oracle" and out["unit"] == "spin flips/ns" and out["value"] > 0 and out["cores"] >= 1
+    st = out["single_thread"]
+    assert st["cores"] == 1 and st["value"] > 0
+    assert st["value"] <= out["value"] * 1.5 or out["cores"] == 1  # one thread is not faster than all
