@@ -413,6 +413,19 @@ def cpu_baseline(target_s):
     return out
 
 
+def run_env(torch):
+    """Where the line was measured: the device name, the HIP and torch versions
+    and the host threads; an item that cannot be read is null."""
+    env = {"gpu": None, "hip": getattr(torch.version, "hip", None), "torch": torch.__version__,
+           "host_threads": len(os.sched_getaffinity(0))}
+    try:
+        if torch.cuda.is_available():
+            env["gpu"] = torch.cuda.get_device_name(0)
+    except RuntimeError:
+        pass
+    return env
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -514,6 +527,7 @@ def main():
         out["muca"] = muca_comparison(torch, mcs, ctx, [int(x) for x in a.muca.split(",")], a.muca_prod)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
+    out["env"] = run_env(torch)
     print(json.dumps(out))
 
 

@@ -41,3 +41,11 @@ def test_cpu_baseline_leg_reports_all_cores_and_one_thread():
     st = out["single_thread"]
     assert st["cores"] == 1 and st["value"] > 0
     assert st["value"] <= out["value"] * 1.5 or out["cores"] == 1  # one thread is not faster than all
+
+
+def test_run_env_fields():
+    import torch
+
+    env = _bench().run_env(torch)
+    assert set(env) == {"gpu", "hip", "torch", "host_threads"} and env["host_threads"] >= 1
+    assert env["torch"] == torch.__version__
