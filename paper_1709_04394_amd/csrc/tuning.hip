@@ -8,7 +8,9 @@
 //   tile <dims> <Lx> <Ly> <Lz> <count> <H> <K> <threads>
 //   pa <L> <G>
 #include <cerrno>
+#include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <tuple>
@@ -31,6 +33,27 @@ std::string strip(const char *line)
     if (b == std::string::npos) return std::string();
     const size_t e = s.find_last_not_of(" \t\r\n");
     return s.substr(b, e - b + 1);
+}
+
+// "<keyword> v0 v1 ... v(n-1)": exactly n decimal integers that fit int32
+bool parse_entry(const std::string &s, const char *keyword, int *v, int n)
+{
+    const size_t kl = std::strlen(keyword);
+    if (s.compare(0, kl, keyword) != 0 || (s.size() > kl && s[kl] != ' ' && s[kl] != '\t')) return false;
+    const char *p = s.c_str() + kl;
+    for (int i = 0; i < n; ++i) {
+        while (*p == ' ' || *p == '\t') ++p;
+        if (!*p) return false;
+        char *end = nullptr;
+        errno = 0;
+        const long long x = std::strtoll(p, &end, 10);
+        if (end == p || errno == ERANGE || x < INT32_MIN || x > INT32_MAX || (*end && *end != ' ' && *end != '\t'))
+            return false;
+        v[i] = (int)x;
+        p = end;
+    }
+    while (*p == ' ' || *p == '\t') ++p;
+    return *p == 0;
 }
 
 }  // namespace
@@ -88,13 +111,11 @@ int mc_tuning_load(mc_ctx *ctx, const char *path)
             continue;
         }
         int v[8];
-        char extra;
         int r;
-        if (std::sscanf(s.c_str(), "tile %d %d %d %d %d %d %d %d %c", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6],
-                        &v[7], &extra) == 8) {
+        if (parse_entry(s, "tile", v, 8)) {
             const mc_geom g = {v[0], v[1], v[2], v[3], MC_INT8, v[4]};
             r = mc_set_tile_plan(&scratch, &g, v[5], v[6], v[7]);
-        } else if (std::sscanf(s.c_str(), "pa %d %d %c", &v[0], &v[1], &extra) == 2) {
+        } else if (parse_entry(s, "pa", v, 2)) {
             r = v[1] == 0 ? fail(&scratch, MC_E_RANGE, "G = 0 is not a setting") : mc_set_pa_group(&scratch, v[0], v[1]);
         } else {
             r = fail(&scratch, MC_E_INVAL, "unknown entry '%s'", s.c_str());

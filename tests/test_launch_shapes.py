@@ -74,6 +74,10 @@ def test_comments_and_blank_lines(pair, tmp_path):
     ("libmcspin-launch-shapes 1\npa 16 32\ntile 2 4096 4096 1 3 16 4 96\n", mcs.MC_E_RANGE, b":3:"),
     ("libmcspin-launch-shapes 1\npa 16 32\ntile 2 5 8 1 1 4 1 64\n", mcs.MC_E_SHAPE, b":3:"),
     ("libmcspin-launch-shapes 1\npa 16 32\n" + "#" * 300 + "\n", mcs.MC_E_INVAL, b"too long"),
+    ("libmcspin-launch-shapes 1\npa 16 32\npa 99999999999 1\n", mcs.MC_E_INVAL, b":3:"),     # beyond int32
+    ("libmcspin-launch-shapes 1\npa 16 32\npa 16 4x\n", mcs.MC_E_INVAL, b":3:"),
+    ("libmcspin-launch-shapes 1\npa 16 32\npa16 4\n", mcs.MC_E_INVAL, b":3:"),
+    ("libmcspin-launch-shapes 1\npa 16 32\ntile 2 64 64 1 1 16 2\n", mcs.MC_E_INVAL, b":3:"),  # 7 numbers
 ])
 def test_rejected_files_change_nothing(pair, tmp_path, body, code, where):
     _, b = pair
