@@ -234,3 +234,17 @@ def test_settle_folds_walkers_into_the_window():
             want[odd] = -want[odd]
         assert np.array_equal(s, want)
     assert E[1] == E[2] == -2 * N and np.all(spins.reshape(W, N)[1] == 1) and np.all(spins.reshape(W, N)[2] == -1)
+
+
+def test_sweeps_resume_from_a_checkpoint():
+    """The state of a run is (spins, E, sweep number): n1 + n2 sweeps equal n1
+    sweeps, then n2 more from sweep n1, with the histograms adding up."""
+    L, W, seed = 8, 20, 41
+    K = oracle.muca_levels(L)
+    lnW = -0.3 * np.sqrt(np.arange(K, dtype=np.float64))[::-1]
+    s1, E1 = oracle.muca_start(L, W, seed, oracle.MUCA_STRATIFIED)
+    s2, E2 = s1.copy(), E1.copy()
+    H = oracle.muca_sweeps(L, s1, E1, lnW, seed, (1 << 32) - 3, 7, True)
+    Ha = oracle.muca_sweeps(L, s2, E2, lnW, seed, (1 << 32) - 3, 3, True)
+    Hb = oracle.muca_sweeps(L, s2, E2, lnW, seed, (1 << 32), 4, True)
+    assert np.array_equal(s1, s2) and np.array_equal(E1, E2) and np.array_equal(H, Ha + Hb)

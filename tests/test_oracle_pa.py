@@ -115,3 +115,15 @@ def test_resampling_step_against_unshifted_weights(dbeta):
     assert abs(pop.lnQ[0] - math.log(w.mean())) <= 1e-12
     # the new population holds the copies in parent order
     assert np.array_equal(pop.E, E0[np.sort(parents)])
+
+
+def test_anneal_resumes_from_a_checkpoint():
+    """The state of an anneal is (population, energies, step number, ln Z so
+    far): 6 steps in one call equal 2 + 4 steps in two calls."""
+    L, R, seed, theta = 8, 150, 12, 2
+    beta = oracle.pa_schedule(6, 0.6)
+    a = oracle.PAPopulation(L, R, 1, seed).advance(beta, theta, 6)
+    b = oracle.PAPopulation(L, R, 1, seed).advance(beta, theta, 2).advance(beta, theta, 4)
+    assert np.array_equal(a.spins, b.spins) and np.array_equal(a.E, b.E)
+    assert a.Ctot == b.Ctot and a.lnQ == b.lnQ and a.lnZ == b.lnZ
+    assert all(np.array_equal(x, y) for x, y in zip(a.hist, b.hist))
