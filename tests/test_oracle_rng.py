@@ -154,3 +154,21 @@ def test_draw_word_follows_the_documented_construction(seed, replica, sweep):
     for j in list(range(20)) + [16383]:
         w = oracle.philox([j >> 2, replica, sweep & 0xFFFFFFFF, (oracle.TAG_MUCA << 24) | (sweep >> 32)], key)
         assert oracle.draw_word(seed, oracle.TAG_MUCA, j, replica, sweep) == int(w[j & 3])
+
+
+def test_weyl_increments_follow_their_definition_in_both_sources():
+    """Philox's key increments are the leading 32 fraction bits of the golden
+    ratio and of sqrt(3): floor(2^32 (phi - 1)) and floor(2^32 (sqrt 3 - 1)),
+    computed here with exact integer square roots.  The oracle and the GPU
+    library each write them down independently; both must match."""
+    import math
+    import re
+
+    w0 = (math.isqrt(5 << 64) - (1 << 32)) // 2  # 2^32 (sqrt 5 - 1) / 2, floored
+    w1 = math.isqrt(3 << 64) - (1 << 32)
+    root = os.path.dirname(HERE)
+    orc = open(os.path.join(root, "oracle", "mcoracle.c")).read()
+    lib = open(os.path.join(root, "paper_1709_04394_amd", "csrc", "common.hpp")).read()
+    got_orc = [int(re.search(r"#define ORC_PHILOX_%s (0x[0-9A-Fa-f]+)u" % n, orc).group(1), 16) for n in ("W0", "W1")]
+    got_lib = [int(re.search(r"kPhilox%s = (0x[0-9A-Fa-f]+)u" % n, lib).group(1), 16) for n in ("W0", "W1")]
+    assert got_orc == [w0, w1] and got_lib == [w0, w1]
