@@ -167,7 +167,12 @@ int mc_measure(mc_ctx *ctx, const mc_geom *geom, const void *spins, const int8_t
  * only, never results (the determinism contract above).  mc_set_tile_plan
  * fixes it for the geometry (dims, extents, count) on this context;
  * mc_get_tile_plan reports the shape in use (the tuned or set one, else a
- * default).  Host-only calls.                                               */
+ * default).  Host-only calls.  A plan needs H >= 1, K >= 1 and threads a
+ * multiple of 64 in 64..1024; in 2D K <= 8, the Lx/64 words of a row either
+ * at most threads or a multiple of it, and (H + 4K) rows of 2 Lx/64 words
+ * in at most 64 KB of LDS; in 3D K <= 4, Lx/64 <= threads, H <= min(Ly, Lz)
+ * and the tile with its couplings in at most 96 KB.  MC_E_RANGE otherwise,
+ * the geometry's own errors as for mc_sweep.                               */
 int mc_set_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t H, int32_t K, int32_t threads);
 int mc_get_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t *H, int32_t *K, int32_t *threads);
 
