@@ -45,8 +45,7 @@
  * (bits 24..31) are TAG_INIT = 1, TAG_SWEEP = 2, TAG_COUPLING = 3,
  * TAG_RESAMPLE = 4, TAG_MUCA = 5, TAG_MLP_INIT = 6, TAG_SWEEP_LO = 7,
  * TAG_EXCHANGE = 9 (8 is reserved); bit 23 holds the half-sweep colour where
- * one is given, bits
- * 0..22 the high bits of a 64-bit sweep number.
+ * one is given, bits 0..22 the high bits of a 64-bit sweep number.
  */
 #ifndef MCSPIN_H
 #define MCSPIN_H
@@ -159,6 +158,23 @@ int mc_sweep_betas(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *
  * [count * lanes][2].  Stream-ordered.                                      */
 int mc_measure(mc_ctx *ctx, const mc_geom *geom, const void *spins, const int8_t *J, int64_t *EM,
                void *stream);
+
+/* The kernel family mc_sweep (per_lattice = 0) or mc_sweep_betas
+ * (per_lattice != 0) runs for a geometry, update rule, presence of couplings
+ * and workspace size, in order of preference: MC_PATH_FUSED_2D / _3D (int8,
+ * Lx a multiple of 64, bit-packed tiles in LDS, several sweeps per launch;
+ * 2D only for Metropolis without couplings; needs mc_sweep_workspace_bytes
+ * of workspace), MC_PATH_SMALL_BITS (int8 lattices of 32-site rows that fit
+ * one workgroup's LDS bit-packed), MC_PATH_SMALL (int8 lattices that fit one
+ * workgroup's LDS), MC_PATH_MSC64 (64-lane words, Lx a multiple of 128),
+ * MC_PATH_GENERIC (one launch per half-sweep).  Results never depend on the
+ * path.  Host only: no device work.  Errors as for mc_sweep's geometry and
+ * rule; MC_E_LAYOUT for per_lattice with MC_MSC64; MC_E_INVAL for a NULL
+ * path.                                                                    */
+enum { MC_PATH_FUSED_2D = 1, MC_PATH_FUSED_3D = 2, MC_PATH_SMALL_BITS = 3, MC_PATH_SMALL = 4,
+       MC_PATH_MSC64 = 5, MC_PATH_GENERIC = 6 };
+int mc_sweep_path(mc_ctx *ctx, const mc_geom *geom, int32_t rule, int32_t has_couplings, int32_t per_lattice,
+                  size_t ws_bytes, int32_t *path);
 
 /* Launch shape of the fused sweeps (int8, Lx a multiple of 64; 2D: J = 1,
  * Metropolis; 3D: Metropolis or heat-bath, with or without couplings): band

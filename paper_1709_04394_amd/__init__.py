@@ -142,6 +142,8 @@ _lib_fns = dict(
                                                  _c.POINTER(_c.c_double), _c.POINTER(_c.c_double),
                                                  _c.POINTER(_c.c_int64), _vp, _c.c_size_t, _vp]),
     mc_set_pa_group=_sig("mc_set_pa_group", _c.c_int, [_vp, _c.c_int32, _c.c_int32]),
+    mc_sweep_path=_sig("mc_sweep_path", _c.c_int, [_vp, _c.POINTER(Geom), _c.c_int32, _c.c_int32, _c.c_int32,
+                                                   _c.c_size_t, _c.POINTER(_c.c_int32)]),
     mc_pt_exchange=_sig("mc_pt_exchange", _c.c_int, [_vp, _c.c_int32, _c.POINTER(_c.c_double),
                                                      _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int32),
                                                      _c.POINTER(_c.c_int32), _c.c_uint64, _c.c_uint64,

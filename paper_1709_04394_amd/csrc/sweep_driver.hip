@@ -141,29 +141,44 @@ static int run_fused(mc_ctx *ctx, const SweepCall &c, const TilePlan &p, int8_t 
     return device_check(ctx, e, "mc_sweep fused launch");
 }
 
+// Which kernel family runs a call, in order of preference: the fused tiles
+// (given a large enough workspace and a usable plan), the bit-packed whole
+// lattice, the int8 whole lattice, the multi-spin-coded kernel, the generic
+// half-sweeps.
+static int sweep_path(mc_ctx *ctx, const SweepCall &c, int layout, bool have_ws, size_t ws_bytes)
+{
+    if ((tile2d_supported(c, layout) || tile3d_supported(c, layout)) && have_ws &&
+        ws_bytes >= fused_workspace_bytes(c.g, layout) && plan_ok(c.g, plan_for(ctx, c.g)))
+        return c.g.dims == 2 ? MC_PATH_FUSED_2D : MC_PATH_FUSED_3D;
+    if (small_bits_supported(c, layout)) return MC_PATH_SMALL_BITS;
+    if (small_supported(c, layout)) return MC_PATH_SMALL;
+    if (msc_fast_supported(c, layout)) return MC_PATH_MSC64;
+    return MC_PATH_GENERIC;
+}
+
 int run_sweeps(mc_ctx *ctx, const SweepCall &c, int layout, void *spins, uint64_t sweep0, int nsweeps,
                int64_t *EM, int64_t em_stride, void *ws, size_t ws_bytes, hipStream_t s)
 {
-    const bool fused = (tile2d_supported(c, layout) || tile3d_supported(c, layout)) && ws &&
-                       ws_bytes >= fused_workspace_bytes(c.g, layout);
-    if (fused) {
-        const TilePlan p = plan_for(ctx, c.g);
-        if (plan_ok(c.g, p))
-            return run_fused(ctx, c, p, (int8_t *)spins, (char *)ws, sweep0, nsweeps, EM, em_stride, s);
-    }
-    if (small_bits_supported(c, layout))
+    switch (sweep_path(ctx, c, layout, ws != nullptr, ws_bytes)) {
+    case MC_PATH_FUSED_2D:
+    case MC_PATH_FUSED_3D:
+        return run_fused(ctx, c, plan_for(ctx, c.g), (int8_t *)spins, (char *)ws, sweep0, nsweeps, EM, em_stride, s);
+    case MC_PATH_SMALL_BITS:
         return device_check(ctx, launch_small_bits(c, (int8_t *)spins, sweep0, nsweeps, EM, em_stride, s),
                             "mc_sweep small bit-packed lattice launch");
-    if (small_supported(c, layout))
+    case MC_PATH_SMALL:
         return device_check(ctx, launch_small(c, (int8_t *)spins, sweep0, nsweeps, EM, em_stride, s),
                             "mc_sweep small-lattice launch");
-    if (msc_fast_supported(c, layout)) {
+    case MC_PATH_MSC64: {
         hipError_t e = EM ? launch_fill_i64(EM, (int64_t)nsweeps * em_stride, 0, s) : hipSuccess;
         for (int t = 0; t < nsweeps && e == hipSuccess; ++t)
             for (int phase = 0; phase < 2 && e == hipSuccess; ++phase)
                 e = launch_msc_phase(c, (uint64_t *)spins, sweep0 + (uint64_t)t, phase, EM ? EM + t * em_stride : nullptr,
                                      s);
         return device_check(ctx, e, "mc_sweep multi-spin launch");
+    }
+    default:
+        break;
     }
     for (int t = 0; t < nsweeps; ++t) {
         const uint64_t sweep = sweep0 + (uint64_t)t;
@@ -184,6 +199,27 @@ int run_sweeps(mc_ctx *ctx, const SweepCall &c, int layout, void *spins, uint64_
 using namespace mcs;
 
 extern "C" {
+
+int mc_sweep_path(mc_ctx *ctx, const mc_geom *geom, int32_t rule, int32_t has_couplings, int32_t per_lattice,
+                  size_t ws_bytes, int32_t *path)
+{
+    if (!ctx) return MC_E_INVAL;
+    int rc = check_geom(ctx, geom, true);
+    if (rc) return rc;
+    if (!path) return fail(ctx, MC_E_INVAL, "path is NULL");
+    if (rule != MC_METROPOLIS && rule != MC_HEATBATH) return fail(ctx, MC_E_INVAL, "unknown rule %d", rule);
+    if (per_lattice && geom->layout != MC_INT8) return fail(ctx, MC_E_LAYOUT, "per-lattice temperatures need MC_INT8");
+    // the selection reads only the shape, the rule and whether couplings and
+    // per-lattice tables are present, never their contents
+    static const int8_t some_coupling = 1;
+    SweepCall c{};
+    c.g = to_geom(geom);
+    c.J = has_couplings ? &some_coupling : nullptr;
+    c.rule = rule;
+    c.per_lattice = per_lattice ? 1 : 0;
+    *path = sweep_path(ctx, c, geom->layout, ws_bytes > 0, ws_bytes);
+    return MC_OK;
+}
 
 int mc_set_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t H, int32_t K, int32_t threads)
 {

@@ -55,7 +55,11 @@ int main(int argc, char **argv)
     CHECK(mc_sweep_betas(ctx, &g2, FAKE, NULL, &sa, betas, NULL, NULL, 0, NULL) == MC_E_RANGE);
     CHECK(mc_sweep_workspace_bytes(&g2) == 2ull * 3 * 4096 * 4096 / 8);
 
-    /* launch shapes */
+    /* kernel family and launch shapes */
+    int32_t path = 0;
+    CHECK(mc_sweep_path(ctx, &g2, MC_METROPOLIS, 0, 0, mc_sweep_workspace_bytes(&g2), &path) == MC_OK &&
+          path == MC_PATH_FUSED_2D);
+    CHECK(mc_sweep_path(ctx, &g2, MC_HEATBATH, 1, 0, 0, &path) == MC_OK && path == MC_PATH_GENERIC);
     CHECK(mc_get_tile_plan(ctx, &g2, &H, &K, &T) == MC_OK);
     CHECK(mc_set_tile_plan(ctx, &g2, 16, 4, 512) == MC_OK);
     CHECK(mc_set_tile_plan(ctx, &g2, 16, 4, 96) == MC_E_RANGE);
