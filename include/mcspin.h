@@ -418,6 +418,18 @@ int mc_muca_run(mc_ctx *ctx, const mc_muca_args *args, const double *lnW_init, i
                 int64_t *H_out, double *lng_out, double *flat_out, mc_muca_stats *stats, void *ws, size_t ws_bytes,
                 void *stream);
 
+/* One step of the weight recursion of mc_muca_run (Eq. weight_modification),
+ * for callers that run their own iterations with mc_muca_sweeps:
+ * ln W'(k) = ln W(k) - ln H(k) where H(k) > 0 (host FP64 libm log), then
+ * ln W' shifted so that ln W'(N/2) = 0 (E = 0).  lnW, lnW_out: host double
+ * [N/2 + 1] (may be the same array); H: host int64 [N/2 + 1], the histogram
+ * of the iteration.  flat_out (or NULL): min/max of H over the window levels
+ * but k = 1, 0 when H is empty, the flatness mc_muca_run tests.  Host only.
+ * Errors: MC_E_SHAPE for an unsupported L; MC_E_INVAL for a NULL pointer;
+ * MC_E_RANGE for a non-finite ln W or a negative count.                    */
+int mc_muca_update(mc_ctx *ctx, int32_t L, const double *lnW, const int64_t *H, double *lnW_out,
+                   double *flat_out);
+
 /* ------------------------------------------------------------------------
  * A small MLP that predicts initial multicanonical weights from what the
  * method itself produced at smaller L: x = (E/N + 1, 32/L - 1) -> tanh(64)

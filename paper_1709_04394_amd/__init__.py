@@ -142,6 +142,9 @@ _lib_fns = dict(
                                                  _c.POINTER(_c.c_double), _c.POINTER(_c.c_double),
                                                  _c.POINTER(_c.c_int64), _vp, _c.c_size_t, _vp]),
     mc_set_pa_group=_sig("mc_set_pa_group", _c.c_int, [_vp, _c.c_int32, _c.c_int32]),
+    mc_muca_update=_sig("mc_muca_update", _c.c_int, [_vp, _c.c_int32, _c.POINTER(_c.c_double),
+                                                     _c.POINTER(_c.c_int64), _c.POINTER(_c.c_double),
+                                                     _c.POINTER(_c.c_double)]),
     mc_sweep_path=_sig("mc_sweep_path", _c.c_int, [_vp, _c.POINTER(Geom), _c.c_int32, _c.c_int32, _c.c_int32,
                                                    _c.c_size_t, _c.POINTER(_c.c_int32)]),
     mc_pt_exchange=_sig("mc_pt_exchange", _c.c_int, [_vp, _c.c_int32, _c.POINTER(_c.c_double),
@@ -311,6 +314,23 @@ class Context:
     def set_pa_group(self, L, G):
         """Replicas per workgroup for populations of extent L (0: built-in rule)."""
         return self._check(_lib.mc_set_pa_group(self._h, L, G), "mc_set_pa_group")
+
+    def muca_update(self, L, lnW, H):
+        """One step of the weight recursion (mc_muca_update): returns the new
+        ln W (float64 [N/2 + 1]) and the flatness min/max of H."""
+        import numpy as np
+
+        K = L * L // 2
+        lnW = np.ascontiguousarray(lnW, dtype=np.float64)
+        H = np.ascontiguousarray(H, dtype=np.int64)
+        if lnW.size != K + 1 or H.size != K + 1:
+            raise ValueError("lnW and H need L^2 / 2 + 1 entries")
+        out = np.empty(K + 1, dtype=np.float64)
+        flat = ctypes.c_double()
+        p = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))
+        self._check(_lib.mc_muca_update(self._h, L, p(lnW, ctypes.c_double), p(H, ctypes.c_int64),
+                                        p(out, ctypes.c_double), ctypes.byref(flat)), "mc_muca_update")
+        return out, flat.value
 
     def pt_exchange(self, beta, E, temp_of, replica_at, seed, round, accepted):
         """One round of replica exchanges (mc_pt_exchange) on numpy arrays:

@@ -113,6 +113,16 @@ int copy_to_host(mc_ctx *ctx, void *dst, const void *src, size_t bytes, hipStrea
     return device_check(ctx, e, "device to host copy");
 }
 
+// One step of the weight recursion (Eq. weight_modification) in logs:
+// W^(n+1) = W^(n) / H^(n) where H > 0, then ln W(E = 0) = 0 (level K).
+void recursion_step(int K, double *lnW, const int64_t *H)
+{
+    for (int k = 0; k <= K; ++k)
+        if (H[k] > 0) lnW[k] = lnW[k] - std::log((double)H[k]);
+    const double ref = lnW[K];
+    for (int k = 0; k <= K; ++k) lnW[k] = lnW[k] - ref;
+}
+
 double flatness(int L, const std::vector<int64_t> &H)
 {
     // all levels of the window but k = 1 (E = -2N + 4 has no state)
@@ -259,11 +269,7 @@ int mc_muca_run(mc_ctx *ctx, const mc_muca_args *a, const double *lnW_init, int8
             if (k != 1 && H[(size_t)k] == 0) covered = false;
         if (covered && (a->rec_rule == 0 || ratio <= prev)) R = std::min(2 * R, Rmax);
         prev = covered ? ratio : 0.0;
-        // W^(n+1) = W^(n) / H^(n) where H > 0, then ln W(E = 0) = 0
-        for (int k = 0; k <= K; ++k)
-            if (H[(size_t)k] > 0) lnW[(size_t)k] = lnW[(size_t)k] - std::log((double)H[(size_t)k]);
-        const double ref = lnW[(size_t)K];
-        for (int k = 0; k <= K; ++k) lnW[(size_t)k] = lnW[(size_t)k] - ref;
+        recursion_step(K, lnW.data(), H.data());
     }
     stats->iterations = it;
     stats->converged = converged ? 1 : 0;
@@ -290,6 +296,25 @@ int mc_muca_run(mc_ctx *ctx, const mc_muca_args *a, const double *lnW_init, int8
         lng_out[k] = H[(size_t)k] > 0 ? std::log((double)H[(size_t)k]) - lnW[(size_t)k] : -INFINITY;
     }
     return converged ? MC_OK : fail(ctx, MC_E_NOTCONV, "not flat after %d iterations (min/max %.3f)", it, ratio);
+}
+
+int mc_muca_update(mc_ctx *ctx, int32_t L, const double *lnW, const int64_t *H, double *lnW_out, double *flat_out)
+{
+    if (!ctx) return MC_E_INVAL;
+    if (!muca_L_supported(L))
+        return fail(ctx, MC_E_SHAPE, "L=%d: multicanonical walkers take L in {4,8,12,16,24,32,48,64,96,128}", L);
+    if (!lnW || !H || !lnW_out) return fail(ctx, MC_E_INVAL, "a pointer argument is NULL");
+    const int K = L * L / 2;
+    for (int k = 0; k <= K; ++k) {
+        if (!std::isfinite(lnW[k])) return fail(ctx, MC_E_RANGE, "lnW[%d] is not finite", k);
+        if (H[k] < 0) return fail(ctx, MC_E_RANGE, "H[%d] is negative", k);
+    }
+    std::vector<double> w(lnW, lnW + K + 1);  // lnW_out may be lnW
+    std::vector<int64_t> h(H, H + K + 1);
+    recursion_step(K, w.data(), h.data());
+    std::copy(w.begin(), w.end(), lnW_out);
+    if (flat_out) *flat_out = flatness(L, h);
+    return MC_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,64 @@
+"""The multicanonical weight recursion as a library call (mc_muca_update,
+host only, no GPU) against the oracle, bit for bit: the new ln W and the
+flatness, with empty levels, in place, and the documented errors."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+
+mcs = pytest.importorskip("paper_1709_04394_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return mcs.Context(0)  # host state only
+
+
+@pytest.mark.parametrize("L", [4, 12, 32, 128])
+def test_matches_oracle(ctx, L):
+    K = L * L // 2
+    rng = np.random.default_rng(L)
+    lnW = rng.normal(0.0, 3.0, size=K + 1).cumsum()
+    H = rng.integers(0, 10 ** 9, size=K + 1).astype(np.int64)
+    H[rng.integers(0, K + 1, size=max(1, K // 10))] = 0  # levels the iteration never reached
+    H[1] = 0  # the level without states
+    got, flat = ctx.muca_update(L, lnW, H)
+    assert np.array_equal(got, oracle.muca_update(L, lnW, H))
+    assert flat == oracle.muca_flatness(L, H)
+    assert got[-1] == 0.0
+    # in place (lnW_out = lnW)
+    w = lnW.copy()
+    p = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))
+    assert mcs._lib.mc_muca_update(ctx._h, L, p(w, ctypes.c_double), p(H, ctypes.c_int64), p(w, ctypes.c_double),
+                                   None) == 0
+    assert np.array_equal(w, got)
+
+
+def test_flat_histogram_and_empty_histogram(ctx):
+    L = 8
+    K = L * L // 2
+    H = np.full(K + 1, 7, dtype=np.int64)
+    H[1] = 0
+    _, flat = ctx.muca_update(L, np.zeros(K + 1), H)
+    assert flat == 1.0
+    w, flat = ctx.muca_update(L, np.arange(K + 1, dtype=np.float64), np.zeros(K + 1, dtype=np.int64))
+    assert flat == 0.0 and np.array_equal(w, np.arange(K + 1) - float(K))
+
+
+def test_errors(ctx):
+    L, K = 8, 32
+    lnW, H = np.zeros(K + 1), np.ones(K + 1, dtype=np.int64)
+    p = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))
+    out = np.zeros(K + 1)
+    call = lambda L_, w, h, o: mcs._lib.mc_muca_update(ctx._h, L_, w, h, o, None)
+    assert call(10, p(lnW, ctypes.c_double), p(H, ctypes.c_int64), p(out, ctypes.c_double)) == mcs.MC_E_SHAPE
+    assert call(L, None, p(H, ctypes.c_int64), p(out, ctypes.c_double)) == mcs.MC_E_INVAL
+    bad = lnW.copy()
+    bad[3] = np.inf
+    assert call(L, p(bad, ctypes.c_double), p(H, ctypes.c_int64), p(out, ctypes.c_double)) == mcs.MC_E_RANGE
+    neg = H.copy()
+    neg[5] = -1
+    assert call(L, p(lnW, ctypes.c_double), p(neg, ctypes.c_int64), p(out, ctypes.c_double)) == mcs.MC_E_RANGE
+    assert not out.any()  # nothing written on error
