@@ -90,6 +90,14 @@ int main(int argc, char **argv)
     CHECK(mc_mlp_training_set(ctx, 2, tl, tw, X, Y, 64, &n) == MC_OK && n == 8 + 32);
     CHECK(mc_mlp_training_set(ctx, 2, tl, tw, X, Y, 10, &n) == MC_E_RANGE);
     CHECK(mc_mlp_param_count() == 4417 && mc_mlp_workspace_bytes(100) > 0);
+    {
+        double uw[33], flat;
+        int64_t uh[33];
+        for (int k = 0; k < 33; ++k) { uw[k] = -0.1 * k; uh[k] = k == 1 ? 0 : 100 + k; }
+        CHECK(mc_muca_update(ctx, 8, uw, uh, uw, &flat) == MC_OK && uw[32] == 0.0 && flat > 0.0);
+        uh[4] = -1;
+        CHECK(mc_muca_update(ctx, 8, uw, uh, uw, NULL) == MC_E_RANGE);
+    }
 
     /* parallel tempering exchange (host only) */
     double tb[3] = {0.1, 0.2, 0.3};
