@@ -110,6 +110,43 @@ SweepTables build_tables(double beta)
     return t;
 }
 
+int check_sweep_args(mc_ctx *ctx, const mc_geom *geom, const void *spins, const mc_sweep_args *args)
+{
+    int rc = check_geom(ctx, geom, true);
+    if (rc) return rc;
+    if (!spins) return fail(ctx, MC_E_INVAL, "spins is NULL");
+    if (!args) return fail(ctx, MC_E_INVAL, "args is NULL");
+    if (args->rule != MC_METROPOLIS && args->rule != MC_HEATBATH)
+        return fail(ctx, MC_E_INVAL, "unknown rule %d", args->rule);
+    if (!(args->beta >= 0.0) || std::isinf(args->beta))
+        return fail(ctx, MC_E_RANGE, "beta must be finite and >= 0");
+    if (args->nsweeps < 0) return fail(ctx, MC_E_RANGE, "nsweeps must be >= 0");
+    if (args->sweep0 + (uint64_t)args->nsweeps >= (1ull << 55))
+        return fail(ctx, MC_E_RANGE, "sweep numbers must stay below 2^55");
+    const uint64_t lanes = geom->layout == MC_MSC64 ? 64 : 1;
+    if ((uint64_t)args->replica0 + lanes * (uint64_t)geom->count > 4294967296ull)
+        return fail(ctx, MC_E_RANGE, "replica ids exceed 32 bits");
+    return MC_OK;
+}
+
+int sweep_dispatch(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *J, const mc_sweep_args *args,
+                   int64_t *EM, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    SweepCall c;
+    c.g = to_geom(geom);
+    c.J = J;
+    c.rule = args->rule;
+    c.seed_lo = (uint32_t)args->seed;
+    c.seed_hi = (uint32_t)(args->seed >> 32);
+    c.replica0 = args->replica0;
+    c.tab = build_tables(args->beta);
+    c.per_lattice = 0;
+    c.tabs = nullptr;
+    const int64_t lanes = geom->layout == MC_MSC64 ? 64 : 1;
+    const int64_t em_stride = 2 * (int64_t)geom->count * lanes;
+    return run_sweeps(ctx, c, geom->layout, spins, args->sweep0, args->nsweeps, EM, em_stride, ws, ws_bytes, s);
+}
+
 }  // namespace mcs
 
 // ============================================================================
@@ -192,36 +229,11 @@ int mc_sweep(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *J, con
              int64_t *EM, void *ws, size_t ws_bytes, void *stream)
 {
     if (!ctx) return MC_E_INVAL;
-    int rc = check_geom(ctx, geom, true);
+    int rc = check_sweep_args(ctx, geom, spins, args);
     if (rc) return rc;
-    if (!spins) return fail(ctx, MC_E_INVAL, "spins is NULL");
-    if (!args) return fail(ctx, MC_E_INVAL, "args is NULL");
-    if (args->rule != MC_METROPOLIS && args->rule != MC_HEATBATH)
-        return fail(ctx, MC_E_INVAL, "unknown rule %d", args->rule);
-    if (!(args->beta >= 0.0) || std::isinf(args->beta))
-        return fail(ctx, MC_E_RANGE, "beta must be finite and >= 0");
-    if (args->nsweeps < 0) return fail(ctx, MC_E_RANGE, "nsweeps must be >= 0");
-    if (args->sweep0 + (uint64_t)args->nsweeps >= (1ull << 55))
-        return fail(ctx, MC_E_RANGE, "sweep numbers must stay below 2^55");
-    const uint64_t lanes = geom->layout == MC_MSC64 ? 64 : 1;
-    if ((uint64_t)args->replica0 + lanes * (uint64_t)geom->count > 4294967296ull)
-        return fail(ctx, MC_E_RANGE, "replica ids exceed 32 bits");
     if (args->nsweeps == 0) return MC_OK;
     if ((rc = set_device(ctx))) return rc;
-
-    SweepCall c;
-    c.g = to_geom(geom);
-    c.J = J;
-    c.rule = args->rule;
-    c.seed_lo = (uint32_t)args->seed;
-    c.seed_hi = (uint32_t)(args->seed >> 32);
-    c.replica0 = args->replica0;
-    c.tab = build_tables(args->beta);
-    c.per_lattice = 0;
-    c.tabs = nullptr;
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t em_stride = 2 * (int64_t)geom->count * (int64_t)lanes;
-    return run_sweeps(ctx, c, geom->layout, spins, args->sweep0, args->nsweeps, EM, em_stride, ws, ws_bytes, s);
+    return sweep_dispatch(ctx, geom, spins, J, args, EM, ws, ws_bytes, (hipStream_t)stream);
 }
 
 int mc_sweep_betas(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *J, const mc_sweep_args *args,
@@ -260,22 +272,7 @@ int mc_sweep_betas(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *
     c.tab = tabs[0];
     c.per_lattice = 1;
     c.tabs = tabs.data();
-    if ((tile2d_supported(c, MC_INT8) || tile3d_supported(c, MC_INT8)) && ws &&
-        ws_bytes >= fused_workspace_bytes(c.g, MC_INT8))
-        return run_sweeps(ctx, c, MC_INT8, spins, a1.sweep0, a1.nsweeps, EM, em_stride, ws, ws_bytes, s);
-    // otherwise one lattice at a time
-    for (int l = 0; l < geom->count; ++l) {
-        SweepCall c1 = c;
-        c1.g.count = 1;
-        c1.replica0 = a1.replica0 + (uint32_t)l;
-        c1.tab = tabs[(size_t)l];
-        c1.per_lattice = 0;
-        c1.tabs = nullptr;
-        rc = run_sweeps(ctx, c1, MC_INT8, (int8_t *)spins + (int64_t)l * c.g.N, a1.sweep0, a1.nsweeps,
-                        EM ? EM + 2 * l : nullptr, em_stride, nullptr, 0, s);
-        if (rc) return rc;
-    }
-    return MC_OK;
+    return run_sweeps_betas(ctx, c, (int8_t *)spins, a1.sweep0, a1.nsweeps, EM, em_stride, ws, ws_bytes, s);
 }
 
 int mc_measure(mc_ctx *ctx, const mc_geom *geom, const void *spins, const int8_t *J, int64_t *EM, void *stream)

@@ -71,6 +71,11 @@ int capture_stream(mc_ctx *ctx, hipStream_t *out);
 int check_geom(mc_ctx *ctx, const mc_geom *g, bool need_count);
 Geom to_geom(const mc_geom *g);
 SweepTables build_tables(double beta);
+// mc_sweep's argument checks (everything but the pointers to J, EM and ws),
+// and its dispatch once they have passed and the device is current.
+int check_sweep_args(mc_ctx *ctx, const mc_geom *geom, const void *spins, const mc_sweep_args *args);
+int sweep_dispatch(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *J, const mc_sweep_args *args,
+                   int64_t *EM, void *ws, size_t ws_bytes, hipStream_t s);
 
 // fused 2D kernel (k_tile2d.hip)
 bool tile2d_supported(const SweepCall &c, int layout);
@@ -112,5 +117,9 @@ hipError_t launch_msc_phase(const SweepCall &c, uint64_t *words, uint64_t sweep,
 size_t fused_workspace_bytes(const Geom &g, int layout);
 int run_sweeps(mc_ctx *ctx, const SweepCall &c, int layout, void *spins, uint64_t sweep0, int nsweeps,
                int64_t *EM, int64_t em_stride, void *ws, size_t ws_bytes, hipStream_t s);
+// Per-lattice temperatures (c.per_lattice, c.tabs): the fused kernels when
+// the geometry, plan and workspace allow, else each lattice alone.
+int run_sweeps_betas(mc_ctx *ctx, const SweepCall &c, int8_t *spins, uint64_t sweep0, int nsweeps, int64_t *EM,
+                     int64_t em_stride, void *ws, size_t ws_bytes, hipStream_t s);
 
 }  // namespace mcs

@@ -156,10 +156,54 @@ static int sweep_path(mc_ctx *ctx, const SweepCall &c, int layout, bool have_ws,
     return MC_PATH_GENERIC;
 }
 
+// The kernel family of a call with per-lattice temperatures: the fused
+// tiles carry one table per lattice; every other family runs the lattices
+// one at a time, each alone with its own table and no workspace.
+static SweepCall single_lattice(const SweepCall &c, int l)
+{
+    SweepCall c1 = c;
+    c1.g.count = 1;
+    c1.replica0 = c.replica0 + (uint32_t)l;
+    if (c.per_lattice) c1.tab = c.tabs[l];
+    c1.per_lattice = 0;
+    c1.tabs = nullptr;
+    return c1;
+}
+
+static int betas_path(mc_ctx *ctx, const SweepCall &c, bool have_ws, size_t ws_bytes)
+{
+    const int p = sweep_path(ctx, c, MC_INT8, have_ws, ws_bytes);
+    if (p == MC_PATH_FUSED_2D || p == MC_PATH_FUSED_3D) return p;
+    SweepCall c1 = c;
+    c1.g.count = 1;
+    c1.per_lattice = 0;
+    c1.tabs = nullptr;
+    return sweep_path(ctx, c1, MC_INT8, false, 0);
+}
+
+int run_sweeps_betas(mc_ctx *ctx, const SweepCall &c, int8_t *spins, uint64_t sweep0, int nsweeps, int64_t *EM,
+                     int64_t em_stride, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    const int p = betas_path(ctx, c, ws != nullptr, ws_bytes);
+    if (p == MC_PATH_FUSED_2D || p == MC_PATH_FUSED_3D)
+        return run_fused(ctx, c, plan_for(ctx, c.g), spins, (char *)ws, sweep0, nsweeps, EM, em_stride, s);
+    for (int l = 0; l < c.g.count; ++l) {
+        const int rc = run_sweeps(ctx, single_lattice(c, l), MC_INT8, spins + (int64_t)l * c.g.N, sweep0, nsweeps,
+                                  EM ? EM + 2 * l : nullptr, em_stride, nullptr, 0, s);
+        if (rc) return rc;
+    }
+    return MC_OK;
+}
+
 int run_sweeps(mc_ctx *ctx, const SweepCall &c, int layout, void *spins, uint64_t sweep0, int nsweeps,
                int64_t *EM, int64_t em_stride, void *ws, size_t ws_bytes, hipStream_t s)
 {
-    switch (sweep_path(ctx, c, layout, ws != nullptr, ws_bytes)) {
+    const int path = sweep_path(ctx, c, layout, ws != nullptr, ws_bytes);
+    // only the fused tiles read per-lattice tables; any other family would
+    // apply the first lattice's table to all of them
+    if (c.per_lattice && path != MC_PATH_FUSED_2D && path != MC_PATH_FUSED_3D)
+        return fail(ctx, MC_E_LAYOUT, "per-lattice temperatures reached a kernel without per-lattice tables");
+    switch (path) {
     case MC_PATH_FUSED_2D:
     case MC_PATH_FUSED_3D:
         return run_fused(ctx, c, plan_for(ctx, c.g), (int8_t *)spins, (char *)ws, sweep0, nsweeps, EM, em_stride, s);
@@ -217,7 +261,7 @@ int mc_sweep_path(mc_ctx *ctx, const mc_geom *geom, int32_t rule, int32_t has_co
     c.J = has_couplings ? &some_coupling : nullptr;
     c.rule = rule;
     c.per_lattice = per_lattice ? 1 : 0;
-    *path = sweep_path(ctx, c, geom->layout, ws_bytes > 0, ws_bytes);
+    *path = per_lattice ? betas_path(ctx, c, ws_bytes > 0, ws_bytes) : sweep_path(ctx, c, geom->layout, ws_bytes > 0, ws_bytes);
     return MC_OK;
 }
 

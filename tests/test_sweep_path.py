@@ -35,7 +35,15 @@ def _path(ctx, dims, L, rule=mcs.METROPOLIS, J=False, per=False, layout=mcs.INT8
     ((3, 256), dict(rule=mcs.HEATBATH), F3),                           # 3D heat-bath 256^3
     ((3, 256), dict(rule=mcs.HEATBATH, per=True, count=4), F3),        # its four runs in one call
     ((3, 32), dict(J=True), SB),                                       # the spin-glass 32^3
-    ((2, 32), dict(per=True), GEN),                                    # per-lattice tables: not the small kernels
+    ((2, 32), dict(per=True), SB),                                     # per-lattice tables, no fused tiles:
+    ((2, 32), dict(per=True, count=3), SB),                            # ... each lattice alone on its own path
+    ((2, 4096), dict(count=3, per=True), F2),                          # the headline call (mc_sweep_betas)
+    ((2, 4096), dict(count=3, per=True, ws=False), GEN),               # ... without a workspace
+    ((3, 256), dict(rule=mcs.HEATBATH, per=True, count=4, ws=False), GEN),
+    ((2, 64), dict(per=True, count=3), F2),
+    ((2, 64), dict(per=True, count=3, ws=False), SM),
+    ((2, (36, 20)), dict(per=True, count=3), SM),                      # Lx not a multiple of 64
+    ((3, 32), dict(per=True, count=2, J=True), SB),
     ((2, 64), dict(ws=False), SM),                                     # a whole small lattice in LDS
     ((2, (96, 64)), dict(), SM),
     ((2, 4096), dict(layout=mcs.MSC64), MSC),                          # 64-lane words, Lx a multiple of 128
