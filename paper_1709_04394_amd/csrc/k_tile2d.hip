@@ -330,14 +330,11 @@ static hipError_t launch_k(const Tile2DArgs &a, int count, int threads, hipStrea
     const size_t lds = tile2d_lds_bytes(a.Lx, a.H, K);
     dim3 grid((unsigned)tiles, (unsigned)count);
     // allow the largest dynamic LDS a plan may ask for (64 KB) next to the
-    // static tie queue
-    static bool attr[2] = {false, false};
-    if (!attr[a.EM ? 1 : 0]) {
-        const void *f = a.EM ? (const void *)k_tile2d<K, true> : (const void *)k_tile2d<K, false>;
-        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-        if (e != hipSuccess) return e;
-        attr[a.EM ? 1 : 0] = true;
-    }
+    // static tie queue, once per device and kernel instance
+    static LdsLimit lim[2];
+    const void *f = a.EM ? (const void *)k_tile2d<K, true> : (const void *)k_tile2d<K, false>;
+    const hipError_t e = lim[a.EM ? 1 : 0].ensure(f, 65536);
+    if (e != hipSuccess) return e;
     if (a.EM) hipLaunchKernelGGL((k_tile2d<K, true>), grid, dim3(threads), lds, s, a);
     else hipLaunchKernelGGL((k_tile2d<K, false>), grid, dim3(threads), lds, s, a);
     return hipGetLastError();
