@@ -123,9 +123,10 @@ def test_generic_kernels_large_odd_shapes(ctx, dims, shape, rule, J):
 
 def test_config_edwards_anderson_32(ctx):
     # 3D +-J spin glass at L = 32, couplings and spins from seed 13, Metropolis
-    # at beta = 1 (the small-lattice kernel: whole lattice in one workgroup)
+    # at beta = 1, the workload's whole 2000 sweeps (the bit-packed whole-
+    # lattice kernel: one workgroup)
     J = oracle.couplings(3, 32, 13)
-    _run_both(ctx, 3, (32, 32, 32), mcs.METROPOLIS, 1.0, 13, 200, J=J)
+    _run_both(ctx, 3, (32, 32, 32), mcs.METROPOLIS, 1.0, 13, 2000, J=J)
 
 
 def test_edwards_anderson(ctx):
