@@ -64,6 +64,22 @@ def run_arm(ctx, L, seed, lnW_init=None, walkers=WALKERS, eq_sweeps=2, rec_sweep
     return r
 
 
+def refined_weights(ctx, L, lnW, H):
+    """The recursion (Eq. weight_modification, mc_muca_update) applied to a
+    production histogram H at the weights lnW: ln W - ln H, i.e. -ln g_est,
+    normalised to 0 at E = 0.  Every level that has states must have been
+    visited (the level without states, k = 1, keeps its weight, which no
+    move can reach)."""
+    H = np.asarray(H, dtype=np.int64)
+    reach = np.ones(H.size, dtype=bool)
+    reach[1] = False
+    if not np.all(H[reach] > 0):
+        raise RuntimeError("L=%d: the production histogram left %d window levels unvisited"
+                           % (L, int(np.sum(H[reach] == 0))))
+    out, _ = ctx.muca_update(L, lnW, H)
+    return out
+
+
 def training_weights(ctx, Ls=TRAIN_L, prod_sweeps=400, seed0=19, **kw):
     """Converged weights at each training size: ln W = -ln g_est from a plain
     run to a flat histogram plus a production run (the recursion applied once
@@ -74,9 +90,7 @@ def training_weights(ctx, Ls=TRAIN_L, prod_sweeps=400, seed0=19, **kw):
         runs[L] = r
         if not r["converged"]:
             raise RuntimeError("plain multicanonical run at L=%d did not converge" % L)
-        lng = r["lng"]
-        lnW = -np.where(np.isfinite(lng), lng, 0.0)
-        out[L] = lnW - lnW[-1]
+        out[L] = refined_weights(ctx, L, r["lnW"], r["H_prod"])
     return out, runs
 
 
@@ -229,16 +243,7 @@ def main(argv=None):
             files = sorted(glob.glob(os.path.join(a.dir, "H_%s_*.npy" % a.arm)))
             if not files:
                 raise SystemExit("no earlier runs of arm %s in %s" % (a.arm, a.dir))
-            Hs = sum(np.load(f) for f in files)
-            # levels never visited have no states (E = -2N + 4 on the torus): no
-            # move enters them, so their weight is copied from the level below
-            seen = Hs > 0
-            if not seen[0] or not seen[-1]:
-                raise SystemExit("an earlier run left an end of the window unvisited")
-            lnWr = np.where(seen, lnW - np.log(np.maximum(Hs, 1)), 0.0)
-            for k in np.flatnonzero(~seen):
-                lnWr[k] = lnWr[k - 1]
-            lnW = lnWr - lnWr[-1]
+            lnW = refined_weights(ctx, L, lnW, sum(np.load(f) for f in files))
             np.save(os.path.join(a.dir, "weights_refined_%s.npy" % a.arm), lnW)
         H = production(ctx, L, lnW, a.seed, a.burn, a.sweeps, label=a.arm)
         np.save(os.path.join(a.dir, "%s_%s_%d.npy" % ("HR" if a.refined else "H", a.arm, a.seed)), H)

@@ -62,3 +62,18 @@ def test_errors(ctx):
     neg[5] = -1
     assert call(L, p(lnW, ctypes.c_double), p(neg, ctypes.c_int64), p(out, ctypes.c_double)) == mcs.MC_E_RANGE
     assert not out.any()  # nothing written on error
+
+
+@pytest.mark.parametrize("L", [8, 32, 128])
+def test_nontrivial_flatness(ctx, L):
+    # every count positive and unequal (but the level without states): the
+    # flatness is a ratio strictly between 0 and 1, compared bit for bit
+    K = L * L // 2
+    rng = np.random.default_rng(100 + L)
+    H = rng.integers(1000, 5000, size=K + 1).astype(np.int64)
+    H[1] = 0
+    lnW = rng.normal(0.0, 2.0, size=K + 1)
+    got, flat = ctx.muca_update(L, lnW, H)
+    assert 0.2 < flat < 1.0
+    assert flat == oracle.muca_flatness(L, H)
+    assert np.array_equal(got, oracle.muca_update(L, lnW, H))
