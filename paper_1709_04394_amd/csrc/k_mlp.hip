@@ -111,22 +111,26 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(const float *params, const f
 }
 
 // Sum the chunk slots in order; mode 0: write gradient and loss; mode 1:
-// Adam step t = *step + 1 on params with moments m, v, and log the loss.
-__global__ void k_mlp_adam(const float *part, int nchunks, int n, float *params, float *m, float *v, int *step,
+// Adam step t on params with moments m, v, and log the loss.  Each slot p
+// (a parameter, or the loss at p = kMlpParams) keeps its own step count in
+// steps[p] and advances it itself, so no other thread reads it and no extra
+// launch per epoch is needed (all counts are equal between epochs).
+__global__ void k_mlp_adam(const float *part, int nchunks, int n, float *params, float *m, float *v, int *steps,
                            float *grad_out, float *loss_out, MlpHyper hp, int mode)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p > kMlpParams) return;
     float g = 0.f;
     for (int c = 0; c < nchunks; ++c) g += part[(size_t)c * (kMlpParams + 1) + p];
-    const int t = *step + 1;
-    if (p == kMlpParams) {
-        if (mode == 0) *loss_out = g / (float)n;
-        else loss_out[t - 1] = g / (float)n;
+    if (mode == 0) {
+        if (p == kMlpParams) *loss_out = g / (float)n;
+        else grad_out[p] = g;
         return;
     }
-    if (mode == 0) {
-        grad_out[p] = g;
+    const int t = steps[p] + 1;
+    steps[p] = t;
+    if (p == kMlpParams) {
+        loss_out[t - 1] = g / (float)n;
         return;
     }
     const float mm = hp.beta1 * m[p] + (1.f - hp.beta1) * g;
@@ -137,8 +141,6 @@ __global__ void k_mlp_adam(const float *part, int nchunks, int n, float *params,
     const float vh = vv / (1.f - powf(hp.beta2, (float)t));
     params[p] -= hp.lr * mh / (sqrtf(vh) + hp.eps);
 }
-
-__global__ void k_mlp_bump(int *step) { *step += 1; }
 
 __global__ void k_mlp_predict(const float *params, const float *X, int n, float *Y)
 {
@@ -161,38 +163,39 @@ __global__ void k_zero_f32(float *p, int n)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0.f;
 }
 
-__global__ void k_zero_i32(int *p) { *p = 0; }
+__global__ void k_zero_i32(int *p, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
 
 int mlp_chunks(int n) { return (n + CH - 1) / CH; }
 
 hipError_t launch_mlp_grad(const float *params, const float *X, const float *Y, int n, float *part, float *grad,
-                           float *loss, int *step_zero, hipStream_t s)
+                           float *loss, hipStream_t s)
 {
     const int nc = mlp_chunks(n);
     hipLaunchKernelGGL(k_mlp_fwdbwd, dim3(nc), dim3(256), 0, s, params, X, Y, n, part);
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, step_zero);
     MlpHyper hp{};
     hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 256) / 256), dim3(256), 0, s, part, nc, n, (float *)nullptr,
-                       (float *)nullptr, (float *)nullptr, step_zero, grad, loss, hp, 0);
+                       (float *)nullptr, (float *)nullptr, (int *)nullptr, grad, loss, hp, 0);
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_train_setup(float *m, float *v, int *step, hipStream_t s)
+hipError_t launch_mlp_train_setup(float *m, float *v, int *steps, hipStream_t s)
 {
     hipLaunchKernelGGL(k_zero_f32, dim3(32), dim3(256), 0, s, m, kMlpParams);
     hipLaunchKernelGGL(k_zero_f32, dim3(32), dim3(256), 0, s, v, kMlpParams);
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, step);
+    hipLaunchKernelGGL(k_zero_i32, dim3(32), dim3(256), 0, s, steps, kMlpParams + 1);
     return hipGetLastError();
 }
 
 hipError_t launch_mlp_epoch(float *params, const float *X, const float *Y, int n, float *part, float *m, float *v,
-                            int *step, float *loss_log, const MlpHyper &hp, hipStream_t s)
+                            int *steps, float *loss_log, const MlpHyper &hp, hipStream_t s)
 {
     const int nc = mlp_chunks(n);
     hipLaunchKernelGGL(k_mlp_fwdbwd, dim3(nc), dim3(256), 0, s, params, X, Y, n, part);
-    hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 256) / 256), dim3(256), 0, s, part, nc, n, params, m, v, step,
+    hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 256) / 256), dim3(256), 0, s, part, nc, n, params, m, v, steps,
                        (float *)nullptr, loss_log, hp, 1);
-    hipLaunchKernelGGL(k_mlp_bump, dim3(1), dim3(1), 0, s, step);
     return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ MlpLayout mlp_layout(int n)
     l.part = off, off += align256((size_t)mlp_chunks(n) * (kMlpParams + 1) * 4);
     l.m = off, off += align256((size_t)kMlpParams * 4);
     l.v = off, off += align256((size_t)kMlpParams * 4);
-    l.step = off, off += 256;
+    l.step = off, off += align256((size_t)(kMlpParams + 1) * 4);
     l.loss = off, off += 256;
     l.total = off;
     return l;
@@ -66,8 +66,7 @@ int mc_mlp_grad(mc_ctx *ctx, const float *params, const float *X, const float *Y
     if (rc) return rc;
     char *w = (char *)ws;
     return device_check(ctx,
-                        launch_mlp_grad(params, X, Y, n, (float *)(w + l.part), grad, loss, (int *)(w + l.step),
-                                        (hipStream_t)stream),
+                        launch_mlp_grad(params, X, Y, n, (float *)(w + l.part), grad, loss, (hipStream_t)stream),
                         "mc_mlp_grad");
 }
 
@@ -91,7 +90,7 @@ int mc_mlp_train(mc_ctx *ctx, const mc_mlp_args *a, const float *X, const float 
     int *step = (int *)(w + l.step);
     const MlpHyper hp{a->lr, a->beta1, a->beta2, a->eps};
     hipError_t e = launch_mlp_train_setup(m, v, step, s);
-    // a graph of up to kChunk epochs, replayed: the epoch counter lives in
+    // a graph of up to kChunk epochs, replayed: the step counts live in
     // device memory, so every replay continues where the last one stopped
     constexpr int kChunk = 500;
     auto run_graph = [&](int epochs, int times) -> hipError_t {
