@@ -395,7 +395,7 @@ def muca_run(L, walkers, seed, eq_sweeps, rec_sweeps, max_iter, prod_sweeps, fla
 
 
 # ---------------------------------------------------------- parallel tempering
-def pt_exchange(beta, E, temp_of, replica_at, seed, rnd, accepted):
+def pt_exchange(beta, E, temp_of, replica_at, seed, rnd, accepted, pt_set=0):
     """One round of replica-exchange moves (Sec. "Parallel Tempering", Eq. pt).
     Temperatures are indexed in order of increasing beta; replica_at[i] is the
     replica held at temperature i and temp_of[a] its inverse.  Round rnd
@@ -403,9 +403,10 @@ def pt_exchange(beta, E, temp_of, replica_at, seed, rnd, accepted):
     a, b the replicas at i and i + 1 the exchange is accepted with probability
     min(1, exp((beta_i - beta_{i+1}) (E_a - E_b))): always when the exponent is
     >= 0, else iff r32 < ceil(exp(exponent) 2^32), r32 = word (i mod 4) of
-    Philox(EXCHANGE, i div 4, 0, rnd).  An accepted exchange swaps the two
-    replicas' temperatures in both maps and counts in accepted[i].  The maps
-    and accepted are updated in place."""
+    Philox(EXCHANGE, i div 4, pt_set, rnd), pt_set the index of this set of
+    replicas among independent sets run side by side (0 for a single set).
+    An accepted exchange swaps the two replicas' temperatures in both maps and
+    counts in accepted[i].  The maps and accepted are updated in place."""
     nT = len(beta)
     for i in range(rnd % 2, nT - 1, 2):
         a, b = replica_at[i], replica_at[i + 1]
@@ -413,30 +414,32 @@ def pt_exchange(beta, E, temp_of, replica_at, seed, rnd, accepted):
         if x >= 0.0:
             acc = True
         else:
-            acc = draw_word(seed, TAG_EXCHANGE, i, 0, rnd) < math.ceil(math.ldexp(math.exp(x), 32))
+            acc = draw_word(seed, TAG_EXCHANGE, i, pt_set, rnd) < math.ceil(math.ldexp(math.exp(x), 32))
         if acc:
             replica_at[i], replica_at[i + 1] = b, a
             temp_of[a], temp_of[b] = i + 1, i
             accepted[i] += 1
 
 
-def pt_run(dims, L, beta, seed, rounds, theta, rule=METROPOLIS, start=HOT):
-    """Parallel tempering of len(beta) replicas of one lattice shape: replica r
-    starts from init(start, seed, replica id r); per round every replica runs
-    theta sweeps at the inverse temperature it holds (replica id r, sweep
-    numbers round theta + t), then pt_exchange acts on the energies after those
+def pt_run(dims, L, beta, seed, rounds, theta, rule=METROPOLIS, start=HOT, pt_set=0):
+    """Parallel tempering of len(beta) = nT replicas of one lattice shape, the
+    set pt_set of independent sets: replica r has replica id pt_set nT + r and
+    starts from init(start, seed, that id); per round every replica runs theta
+    sweeps at the inverse temperature it holds (its replica id, sweep numbers
+    round theta + t), then pt_exchange acts on the energies after those
     sweeps.  Returns the energies seen at each temperature per round ([rounds]
     [nT], before the exchange), the final maps and the acceptance counts."""
     nT = len(beta)
-    spins = [init(dims, L, start, seed, r) for r in range(nT)]
+    rid = [pt_set * nT + r for r in range(nT)]
+    spins = [init(dims, L, start, seed, rid[r]) for r in range(nT)]
     temp_of, replica_at = list(range(nT)), list(range(nT))
     accepted = [0] * (nT - 1)
     E = np.zeros(nT, dtype=np.int64)
     E_at = np.zeros((rounds, nT), dtype=np.int64)
     for rnd in range(rounds):
         for r in range(nT):
-            EM = sweep(dims, L, spins[r], beta[temp_of[r]], seed, r, rnd * theta, theta, rule=rule)
+            EM = sweep(dims, L, spins[r], beta[temp_of[r]], seed, rid[r], rnd * theta, theta, rule=rule)
             E[r] = EM[-1, 0] if theta > 0 else measure(dims, L, spins[r])[0]
         E_at[rnd] = [E[replica_at[i]] for i in range(nT)]
-        pt_exchange(beta, E, temp_of, replica_at, seed, rnd, accepted)
+        pt_exchange(beta, E, temp_of, replica_at, seed, rnd, accepted, pt_set)
     return dict(E_at=E_at, temp_of=temp_of, replica_at=replica_at, accepted=accepted, spins=spins)

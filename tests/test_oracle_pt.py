@@ -80,3 +80,27 @@ def test_full_run_on_4x4_against_exact_distributions():
         assert abs(rate - want) < 0.03, (i, rate, want)
     assert sorted(r["replica_at"]) == list(range(len(beta)))
     assert all(r["replica_at"][r["temp_of"][a]] == a for a in range(len(beta)))
+
+
+def test_exchange_draw_of_a_set_is_keyed_by_the_set_index():
+    # two temperatures, E_a - E_b = 8 at beta 0.3, 0.5: x = -1.6, accepted iff
+    # word 0 of Philox(EXCHANGE, 0, set, round) < ceil(exp(-1.6) 2^32)
+    T = math.ceil(math.ldexp(math.exp((0.3 - 0.5) * 8.0), 32))
+    for pt_set in (0, 1, 7):
+        for rnd in range(0, 40, 2):  # even rounds propose pair 0
+            t, r, acc = [0, 1], [0, 1], [0]
+            oracle.pt_exchange([0.3, 0.5], [8, 0], t, r, 99, rnd, acc, pt_set)
+            want = oracle.draw_word(99, oracle.TAG_EXCHANGE, 0, pt_set, rnd) < T
+            assert acc[0] == int(want) and (r == [1, 0]) == want
+
+
+def test_sets_start_from_their_own_replica_ids():
+    # set 2 of three-temperature sets: replica r is replica id 6 + r, so before
+    # the first exchange (identity maps) temperature r shows that replica's
+    # energy after theta sweeps of its own stream
+    beta, seed, theta = [0.2, 0.4, 0.6], 5, 2
+    b = oracle.pt_run(2, 4, beta, seed, 3, theta, pt_set=2)
+    for r in range(3):
+        s = oracle.init(2, 4, oracle.HOT, seed, 6 + r)
+        em = oracle.sweep(2, 4, s, beta[r], seed, 6 + r, 0, theta)
+        assert b["E_at"][0][r] == em[-1, 0]
