@@ -74,6 +74,8 @@ def lib():
                                                      ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, u8p]
         L.orc_sweep_q3.argtypes = [ctypes.c_int, u8p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
                                    ctypes.c_uint64, ctypes.c_int, u8p]
+        L.orc_sweep_dcb.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u8p, ctypes.c_double, ctypes.c_uint64,
+                                    ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, u8p]
         L.orc_canonical_scan.argtypes = [u8p, u8p, ctypes.c_int64]
         L.orc_canonical_scan.restype = None
         L.orc_pa_init.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, u8p, u8p]
@@ -184,6 +186,16 @@ def sweep(dims, L, s, beta, seed, replica, sweep0, nsweeps, rule=METROPOLIS, J=N
 def sweep_q3(L, s, beta, seed, replica, sweep0, nsweeps, record=True):
     EM = np.zeros((nsweeps, 2), dtype=np.int64) if record else None
     _check(lib().orc_sweep_q3(L, _p(s), float(beta), seed, replica, sweep0, nsweeps, _p(EM)), "sweep_q3")
+    return EM
+
+
+def sweep_dcb(L, s, beta, seed, replica, sweep0, nsweeps, T, k, record=True):
+    """Double-checkerboard Metropolis sweeps of the L x L ferromagnet with
+    T x T tiles and k hits per tile (orc_sweep_dcb), in place on int8 s;
+    returns EM [n, 2] or None."""
+    assert s.dtype == np.int8 and s.flags.c_contiguous and s.size == L * L
+    EM = np.zeros((nsweeps, 2), dtype=np.int64) if record else None
+    _check(lib().orc_sweep_dcb(L, T, k, _p(s), float(beta), seed, replica, sweep0, nsweeps, _p(EM)), "sweep_dcb")
     return EM
 
 

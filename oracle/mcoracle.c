@@ -20,6 +20,8 @@
  *   energy / magnetisation ... Eq. (ising_model) with h_i = 0
  *   checkerboard sweeps ...... Sec. "Checkerboard scheme" (even sub-lattice,
  *                              then odd sub-lattice; Metropolis or heat-bath)
+ *   double checkerboard ...... Sec. "Checkerboard scheme" (tiles in a coarse
+ *                              checkerboard, k hits per tile)
  *   population annealing ..... Sec. "Population annealing", Eq. (Q)
  *   multicanonical sweeps .... Sec. "Multicanonical simulations", Eq. (muca),
  *                              sequential site order, count-again rule
@@ -329,6 +331,55 @@ int orc_sweep_q3(int L, int8_t *s, double beta, uint64_t seed, uint32_t replica,
                     int dE = 2 * s[i] * h;
                     if (dE <= 0 || (uint64_t)r < Tm[dE / 4]) s[i] = (int8_t)-s[i];
                 }
+        if (EM) orc_measure(2, L, L, 1, s, NULL, &EM[2 * t], &EM[2 * t + 1]);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Double-checkerboard sweep with k hits per tile (Sec. "Checkerboard scheme":
+ * the two-level decomposition of the right panel of Fig. checkerboard, and
+ * multi-hit updates).  The L x L torus is cut into T x T tiles; the tile
+ * holding site (x, y) has coarse colour (x/T + y/T) mod 2, and L/T is even so
+ * that the tiles form a checkerboard on the torus.  One sweep first updates
+ * every tile of coarse colour 0, then every tile of coarse colour 1.  Tiles
+ * of one coarse colour share no bond, so they are updated independently
+ * while the spins of the other colour's tiles stay fixed; each such tile
+ * takes k rounds of its own checkerboard update (its sites with x + y even,
+ * then those with x + y odd).  Every site is therefore updated k times per
+ * sweep.  Readings where the paper leaves a choice: coarse colour 0 first,
+ * even sites first within a round, and the random numbers: hit h (0..k-1) of
+ * sweep t of a site draws exactly what the plain checkerboard sweep numbered
+ * t k + h draws for it (same-colour index j = i >> 1, its colour c).  Sites of
+ * one coarse and one fine colour have no common bond, so updating them one
+ * after the other in place equals updating them simultaneously.
+ * Metropolis, J = 1.  EM (optional) receives (E, M) after every sweep.      */
+int orc_sweep_dcb(int L, int T, int k, int8_t *s, double beta, uint64_t seed, uint32_t replica,
+                  uint64_t sweep0, int nsweeps, int64_t *EM)
+{
+    if (L < 4 || T < 2 || (T & 1) || L % T || ((L / T) & 1) || k < 1 || nsweeps < 0) return -1;
+    orc_geom g = mkgeom(2, L, L, 1);
+    uint64_t Tm[4];
+    orc_metropolis_table(beta, 3, Tm);
+    for (int t = 0; t < nsweeps; ++t) {
+        uint64_t sweep = sweep0 + (uint64_t)t;
+        for (int P = 0; P < 2; ++P)
+            for (int h = 0; h < k; ++h) {
+                uint64_t draw_sweep = sweep * (uint64_t)k + (uint64_t)h;
+                for (int c = 0; c < 2; ++c) {
+                    #pragma omp parallel for schedule(static) if (g.N >= 8192)
+                    for (int y = 0; y < L; ++y)
+                        for (int x = 0; x < L; ++x) {
+                            if (((x / T + y / T) & 1) != P || ((x + y) & 1) != c) continue;
+                            int64_t i = site(&g, x, y, 0);
+                            int hf = local_field(&g, s, NULL, x, y, 0);
+                            uint32_t r = orc_draw32(seed, ORC_TAG_SWEEP, ORC_TAG_SWEEP_LO,
+                                                    (uint32_t)(i >> 1), replica, draw_sweep, (uint32_t)c);
+                            int dE = 2 * s[i] * hf;
+                            if (dE <= 0 || (uint64_t)r < Tm[dE / 4]) s[i] = (int8_t)-s[i];
+                        }
+                }
+            }
         if (EM) orc_measure(2, L, L, 1, s, NULL, &EM[2 * t], &EM[2 * t + 1]);
     }
     return 0;

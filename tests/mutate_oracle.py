@@ -106,9 +106,25 @@ MUTANTS = [
     ("pt: every pair every round", "for i in range(rnd % 2, nT - 1, 2):", "for i in range(0, nT - 1):",
      "oracle/__init__.py"),
     ("pt: one map not updated", "            temp_of[a], temp_of[b] = i + 1, i\n", "", "oracle/__init__.py"),
+    ("pt: sets share the exchange stream", "draw_word(seed, TAG_EXCHANGE, i, pt_set, rnd)",
+     "draw_word(seed, TAG_EXCHANGE, i, 0, rnd)", "oracle/__init__.py"),
+    ("pt: sets share replica ids", "rid = [pt_set * nT + r for r in range(nT)]", "rid = list(range(nT))",
+     "oracle/__init__.py"),
+    # double checkerboard with k hits (Sec. "Checkerboard scheme")
+    ("dcb: second coarse colour first", "if (((x / T + y / T) & 1) != P || ((x + y) & 1) != c) continue;",
+     "if (((x / T + y / T + 1) & 1) != P || ((x + y) & 1) != c) continue;"),
+    ("dcb: one hit fewer", "for (int h = 0; h < k; ++h) {\n                uint64_t draw_sweep",
+     "for (int h = 1; h < k; ++h) {\n                uint64_t draw_sweep"),
+    ("dcb: hits share one draw", "uint64_t draw_sweep = sweep * (uint64_t)k + (uint64_t)h;",
+     "uint64_t draw_sweep = sweep * (uint64_t)k;"),
+    ("dcb: tiles by row bands", "if (((x / T + y / T) & 1) != P || ((x + y) & 1) != c) continue;",
+     "if (((y / T) & 1) != P || ((x + y) & 1) != c) continue;"),
+    ("dcb: odd sites first", "if (((x / T + y / T) & 1) != P || ((x + y) & 1) != c) continue;",
+     "if (((x / T + y / T) & 1) != P || ((x + y + 1) & 1) != c) continue;"),
 ]
 
-PIN_TESTS = ["tests/test_golden_lng.py", "tests/test_oracle_exact.py", "tests/test_oracle_mlp.py",
+PIN_TESTS = ["tests/test_golden_lng.py", "tests/test_oracle_dcb.py", "tests/test_oracle_exact.py",
+             "tests/test_oracle_mlp.py",
              "tests/test_oracle_muca.py", "tests/test_oracle_pa.py", "tests/test_oracle_pt.py",
              "tests/test_oracle_rng.py", "tests/test_oracle_streams.py", "tests/test_oracle_sweep.py",
              "tests/test_oracle_tables.py"]
@@ -124,6 +140,10 @@ def _copy_tree(dst):
             shutil.copytree(src, os.path.join(dst, "tests", "golden"))
         elif name in ("conftest.py", "philox_rocrand_kat.cpp") or "tests/" + name in PIN_TESTS:
             shutil.copy(src, os.path.join(dst, "tests", name))
+    # the Weyl-increment pin reads the library's constants header as text
+    os.makedirs(os.path.join(dst, "paper_1709_04394_amd", "csrc"))
+    shutil.copy(os.path.join(ROOT, "paper_1709_04394_amd", "csrc", "common.hpp"),
+                os.path.join(dst, "paper_1709_04394_amd", "csrc", "common.hpp"))
 
 
 def run_mutant(m):
