@@ -35,7 +35,7 @@ def test_L16_matches_fresh_computation():
     assert np.max(np.abs(got[fin] - ref[fin])) <= 1e-12 * np.max(np.abs(ref[fin]))
 
 
-@pytest.mark.parametrize("L", [16, 64, 96, 128])
+@pytest.mark.parametrize("L", [16, 24, 32, 48, 64, 96, 128])
 def test_closed_form_levels_and_window_sum(L):
     N = L * L
     lng = _load(L)
@@ -52,6 +52,13 @@ def test_closed_form_levels_and_window_sum(L):
 
 
 def test_entropy_density_at_zero_energy_grows_to_ln2():
-    s = [_load(L)[-1] / (L * L) for L in (16, 64, 96, 128)]
+    s = [_load(L)[-1] / (L * L) for L in (16, 24, 32, 48, 64, 96, 128)]
     assert all(a < b for a, b in zip(s, s[1:]))
     assert math.log(2.0) - s[-1] < 1e-3
+
+
+@pytest.mark.parametrize("L,want", [(24, 0.687841305184), (48, 0.691519512433), (64, 0.692161353360)])
+def test_entropy_density_at_zero_energy_independent_values(L, want):
+    # ln g(0) / N as computed independently (arbitrary-precision evaluation of
+    # the same exact count, 12 significant digits)
+    assert abs(_load(L)[-1] / (L * L) - want) < 2e-12
