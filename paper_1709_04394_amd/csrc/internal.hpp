@@ -7,6 +7,7 @@
 #include <map>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "../../include/mcspin.h"
 #include "common.hpp"
@@ -24,6 +25,24 @@ struct TilePlan {
 
 }  // namespace mcs
 
+namespace mcs {
+
+// An instantiated graph kept for reuse, with the bytes of every input that
+// shaped it: a later call with the same inputs launches it again as it is.
+struct GraphCache {
+    std::vector<unsigned char> key;
+    hipGraphExec_t exec = nullptr;
+    void reset()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        key.clear();
+    }
+    ~GraphCache() { reset(); }
+};
+
+}  // namespace mcs
+
 struct mc_ctx {
     int device = 0;
     std::string last_error;
@@ -35,8 +54,13 @@ struct mc_ctx {
     // stream on which launch sequences are recorded into hipGraphs (created
     // on first use, default priority, destroyed with the context)
     hipStream_t capture = nullptr;
+    // the last population-annealing graph (mc_pa_anneal) and tempering graph
+    // (mc_pt_run)
+    mcs::GraphCache pa_graph, pt_graph;
     ~mc_ctx()
     {
+        pa_graph.reset();
+        pt_graph.reset();
         if (capture) (void)hipStreamDestroy(capture);
     }
 };
@@ -110,6 +134,20 @@ hipError_t launch_small(const SweepCall &c, int8_t *spins, uint64_t sweep0, int 
 // 64-lane multi-spin-coded half-sweep with fused per-lane E, M (k_msc.hip)
 bool msc_fast_supported(const SweepCall &c, int layout);
 hipError_t launch_msc_phase(const SweepCall &c, uint64_t *words, uint64_t sweep, int phase, int64_t *EM,
+                            hipStream_t s);
+
+// Whole lattices in one workgroup's LDS (population annealing, tempering):
+// the extents they take, LDS words per row and parity, and lattices per
+// workgroup (set on the context, tuned, or the built-in rule).
+bool pa_L_ok(int L);
+int pa_words_per_row(int L);
+int pa_group_for(const mc_ctx *ctx, int L);
+
+// double-checkerboard multi-hit sweeps (k_dcb.hip): one launch updates every
+// tile of one coarse colour of the packed lattices in place
+size_t dcb_lds_bytes(int T);
+hipError_t launch_dcb_phase(uint32_t *packed, int L, int T, int count, int coarse, int hits, uint32_t replica0,
+                            uint64_t sweep, uint32_t seed_lo, uint32_t seed_hi, const SweepTables &tab, int64_t *EM,
                             hipStream_t s);
 
 // Sweep driver: chooses the fused kernel when the geometry and the workspace

@@ -19,6 +19,7 @@ struct PaPop {
     int32_t *Enew;          // energies of nxt
     double *x, *cmax;       // [R] scan scratch
     int32_t *n, *newparent; // [R] copy numbers, parent of each new slot
+    int32_t *done;          // resampling workgroups finished in this step (0 between steps)
     int64_t *hist;          // [rows][N + 1]
     double *ctot;           // [nsteps]
 };

@@ -11,43 +11,13 @@
 
 using namespace mcs;
 
-namespace {
-
-size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
-
-struct PaLayout {
-    size_t wtab = 0, total = 0;
-    std::vector<size_t> E, Enew, x, cmax, n, newparent, ctot, hist;
-};
+namespace mcs {
 
 bool pa_L_ok(int L)
 {
     if (L < 4 || (L & 1)) return false;
     if (L <= 64) return (L & (L - 1)) == 0 || L == 64;  // 4, 8, 16, 32, 64
     return L % 64 == 0 && L <= 512;
-}
-
-PaLayout pa_layout(const mc_pa_args *a)
-{
-    PaLayout lay;
-    int nmax = 0;
-    for (int p = 0; p < a->npop; ++p) nmax = std::max(nmax, a->L[p] * a->L[p]);
-    size_t off = 0;
-    lay.wtab = off;
-    off += align256((size_t)a->nsteps * (size_t)(nmax + 1) * 8);
-    for (int p = 0; p < a->npop; ++p) {
-        const size_t R = (size_t)a->R, N = (size_t)a->L[p] * a->L[p];
-        lay.E.push_back(off), off += align256(R * 4);
-        lay.Enew.push_back(off), off += align256(R * 4);
-        lay.x.push_back(off), off += align256(R * 8);
-        lay.cmax.push_back(off), off += align256(R * 8);
-        lay.n.push_back(off), off += align256(R * 4);
-        lay.newparent.push_back(off), off += align256(R * 4);
-        lay.ctot.push_back(off), off += align256((size_t)std::max(1, a->nsteps) * 8);
-        lay.hist.push_back(off), off += align256((size_t)(a->nsteps + 1) * (N + 1) * 8);
-    }
-    lay.total = off;
-    return lay;
 }
 
 int pa_words_per_row(int L) { return L >= 64 ? L / 64 : 1; }
@@ -69,6 +39,41 @@ int pa_group_for(const mc_ctx *ctx, int L)
 {
     const auto it = ctx->pa_groups.find(L);
     return it != ctx->pa_groups.end() ? it->second : pa_default_group(L);
+}
+
+}  // namespace mcs
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct PaLayout {
+    size_t wtab = 0, total = 0;
+    std::vector<size_t> E, Enew, x, cmax, n, newparent, ctot, hist, done;
+};
+
+PaLayout pa_layout(const mc_pa_args *a)
+{
+    PaLayout lay;
+    int nmax = 0;
+    for (int p = 0; p < a->npop; ++p) nmax = std::max(nmax, a->L[p] * a->L[p]);
+    size_t off = 0;
+    lay.wtab = off;
+    off += align256((size_t)a->nsteps * (size_t)(nmax + 1) * 8);
+    for (int p = 0; p < a->npop; ++p) {
+        const size_t R = (size_t)a->R, N = (size_t)a->L[p] * a->L[p];
+        lay.E.push_back(off), off += align256(R * 4);
+        lay.Enew.push_back(off), off += align256(R * 4);
+        lay.x.push_back(off), off += align256(R * 8);
+        lay.cmax.push_back(off), off += align256(R * 8);
+        lay.n.push_back(off), off += align256(R * 4);
+        lay.newparent.push_back(off), off += align256(R * 4);
+        lay.ctot.push_back(off), off += align256((size_t)std::max(1, a->nsteps) * 8);
+        lay.hist.push_back(off), off += align256((size_t)(a->nsteps + 1) * (N + 1) * 8);
+        lay.done.push_back(off), off += 256;
+    }
+    lay.total = off;
+    return lay;
 }
 
 int check_pa(mc_ctx *ctx, const mc_pa_args *a)
@@ -156,7 +161,9 @@ int mc_pa_anneal(mc_ctx *ctx, const mc_pa_args *a, void *const *pop_spins, doubl
         P.newparent = (int32_t *)(w + lay.newparent[p]);
         P.ctot = (double *)(w + lay.ctot[p]);
         P.hist = (int64_t *)(w + lay.hist[p]);
+        P.done = (int32_t *)(w + lay.done[p]);
         if (e == hipSuccess) e = launch_fill_i64(P.hist, (int64_t)(a->nsteps + 1) * (P.N + 1), 0, s);
+        if (e == hipSuccess) e = launch_fill_i64((int64_t *)P.done, 1, 0, s);
     }
     if (e == hipSuccess && a->step_first == 1)
         for (int p = 0; p < a->npop && e == hipSuccess; ++p) {
@@ -165,16 +172,32 @@ int mc_pa_anneal(mc_ctx *ctx, const mc_pa_args *a, void *const *pop_spins, doubl
         }
     if (e != hipSuccess) return device_check(ctx, e, "mc_pa_anneal setup");
 
-    // capture the measuring pass and every step in one graph; the caller's
-    // stream may be the legacy default stream, which cannot be captured, so
-    // the kernels are recorded on the context's own capture stream and the
-    // graph is launched on the caller's stream
+    // the measuring pass and every step as one graph.  The caller's stream may
+    // be the legacy default stream, which cannot be captured, so the kernels
+    // are recorded on the context's own capture stream and the graph is
+    // launched on the caller's stream.  The instantiated graph stays in the
+    // context: a call whose inputs are byte for byte those of the previous
+    // one (arguments, schedule, buffers, launch shape) launches it again.
+    std::vector<unsigned char> key;
+    auto put = [&key](const void *p, size_t n) {
+        key.insert(key.end(), (const unsigned char *)p, (const unsigned char *)p + n);
+    };
+    put(&ctx->device, sizeof ctx->device);
+    const int64_t fields[6] = {a->npop, a->R, a->theta, (int64_t)a->seed, a->step_first, a->nsteps};
+    put(fields, sizeof fields);
+    put(a->L, sizeof(int32_t) * a->npop);
+    put(a->beta, sizeof(double) * (size_t)(a->step_first + a->nsteps));
+    put(pop_spins, sizeof(void *) * a->npop);
+    put(&ws, sizeof ws);
+    for (int p = 0; p < a->npop; ++p) put(&st.pop[p].G, sizeof st.pop[p].G);
+    const bool reuse = ctx->pa_graph.exec && ctx->pa_graph.key == key;
     hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraphExec_t exec = reuse ? ctx->pa_graph.exec : nullptr;
+    if (!reuse) ctx->pa_graph.reset();
     if ((rc = capture_stream(ctx, &s_cap))) return rc;
     hipStream_t s_rec = s;
     s = s_cap;
-    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (!reuse) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     int half = 0;  // which half of each population buffer holds the current population
     auto bind = [&](PaStep &x) {
         for (int p = 0; p < a->npop; ++p) {
@@ -187,7 +210,8 @@ int mc_pa_anneal(mc_ctx *ctx, const mc_pa_args *a, void *const *pop_spins, doubl
             P.Enew = (int32_t *)(w + (half ? lay.E[p] : lay.Enew[p]));
         }
     };
-    if (e == hipSuccess) {
+    if (e == hipSuccess && reuse) half = (1 + a->nsteps) & 1;  // as after the recording below
+    if (e == hipSuccess && !reuse) {
         PaStep m = st;
         bind(m);
         m.identity = 1;
@@ -202,7 +226,7 @@ int mc_pa_anneal(mc_ctx *ctx, const mc_pa_args *a, void *const *pop_spins, doubl
         e = launch_pa_step(m, a->R, blocks, s);
         half ^= 1;
     }
-    for (int s_ = 0; s_ < a->nsteps && e == hipSuccess; ++s_) {
+    for (int s_ = 0; s_ < a->nsteps && e == hipSuccess && !reuse; ++s_) {
         const int i = a->step_first + s_;
         PaStep x = st;
         bind(x);
@@ -217,10 +241,20 @@ int mc_pa_anneal(mc_ctx *ctx, const mc_pa_args *a, void *const *pop_spins, doubl
         e = launch_pa_step(x, a->R, blocks, s);
         half ^= 1;
     }
-    hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (!reuse) {
+        const hipError_t ec = hipStreamEndCapture(s, &graph);
+        if (e == hipSuccess) e = ec;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e == hipSuccess) {
+            ctx->pa_graph.exec = exec;
+            ctx->pa_graph.key = key;
+        } else if (exec) {
+            (void)hipGraphExecDestroy(exec);
+            exec = nullptr;
+        }
+    }
     s = s_rec;
-    if (e == hipSuccess) e = ec;
-    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e == hipSuccess) e = hipGraphLaunch(exec, s);
     // the final population goes back to the first half of each buffer
     if (e == hipSuccess && half)
@@ -239,9 +273,10 @@ int mc_pa_anneal(mc_ctx *ctx, const mc_pa_args *a, void *const *pop_spins, doubl
                                hipMemcpyDeviceToHost, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return device_check(ctx, e, "mc_pa_anneal");
+    if (e != hipSuccess) {
+        ctx->pa_graph.reset();
+        return device_check(ctx, e, "mc_pa_anneal");
+    }
 
     // ln Q_i = log(C_total / R) + 2N dbeta_i;  ln Z_i = ln Z_{i-1} + ln Q_i,
     // ln Z(beta_0 = 0) = N ln 2 on a fresh anneal, else lnZ[p][0] as given

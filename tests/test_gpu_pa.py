@@ -137,3 +137,25 @@ def test_pa_tuner_picks_admissible_groups_and_keeps_results(ctx):
             ctx.set_pa_group(L, 0)
     opops = [oracle.PAPopulation(L, R, p, seed).advance(beta, theta, nsteps) for p, L in enumerate(Ls)]
     _compare(Ls, R, res, pops, opops, nsteps)
+
+
+def test_pa_repeated_identical_calls_reuse_the_graph(ctx):
+    """The context keeps the instantiated graph of the last anneal and launches
+    it again for a call with the same inputs: three identical calls, with the
+    workspace overwritten and other work on the device between them, all give
+    the oracle's results; a call with other inputs in between rebuilds it."""
+    Ls, R, theta, nsteps, seed = [16, 64], 200, 2, 4, 31
+    beta = np.array([i * 0.02 for i in range(nsteps + 1)])
+    pops = ctx.pa_population_tensors(Ls, R)
+    ws = torch.empty(ctx.pa_workspace_bytes(Ls, R, theta, beta), dtype=torch.uint8, device="cuda")
+    opops = [oracle.PAPopulation(L, R, p, seed).advance(beta, theta, nsteps) for p, L in enumerate(Ls)]
+    for rep in range(3):
+        res = ctx.pa_anneal(Ls, R, theta, seed, beta, pops, ws=ws)
+        _compare(Ls, R, res, pops, opops, nsteps)
+        ws.fill_(0xA5)
+        for t in pops:
+            t.fill_(3)
+        torch.cuda.synchronize()
+        if rep == 1:
+            other = ctx.pa_anneal(Ls, R, theta, seed + 1, beta, pops, ws=ws)
+            assert not np.array_equal(other["Ctot"], res["Ctot"])
