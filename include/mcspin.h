@@ -20,7 +20,8 @@
  *   - Stream-ordered calls (mc_init, mc_couplings, mc_sweep, mc_measure,
  *     mc_muca_sweeps, mc_mlp_*) return once their work is enqueued; device
  *     buffers must stay alive until the stream has passed the call.  Calls that
- *     return host results (mc_pa_anneal, mc_muca_run) synchronise the stream.
+ *     return host results (mc_pa_anneal, mc_pt_run, mc_muca_run) synchronise
+ *     the stream.
  *   - Determinism: every output is a pure function of the inputs, the seed and
  *     the sweep numbers.  It does not depend on launch shape, tile choice, the
  *     number of lattices per launch or the run (Sec. "Random number
@@ -153,6 +154,29 @@ int mc_sweep(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *J, con
  * them (taller bands, less redone halo).                                   */
 int mc_sweep_betas(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *J, const mc_sweep_args *args,
                    const double *betas, int64_t *EM, void *ws, size_t ws_bytes, void *stream);
+
+/* Double-checkerboard Metropolis sweeps with `hits` updates per tile load
+ * (Sec. "Checkerboard scheme": the two-level "double checkerboard" of the
+ * right panel of Fig. checkerboard, and multi-hit updates) of 2D L x L
+ * ferromagnets (J = 1), MC_INT8, L a multiple of 64 up to 16384.  The
+ * lattice is cut into tile x tile tiles (tile in {64, 128, 256, 512}, L /
+ * tile even) whose coarse colour is (x/tile + y/tile) mod 2.  One sweep
+ * updates every tile of coarse colour 0, then every tile of colour 1; each
+ * tile, with the other colour's spins fixed, takes `hits` rounds of its own
+ * checkerboard (sites with x + y even, then odd), so every site is updated
+ * `hits` times per sweep.  Hit h of sweep t of a site draws exactly the r32
+ * that mc_sweep's sweep number t hits + h draws for it (replica r, same-
+ * colour index, colour).  This is a different Markov chain from mc_sweep's
+ * (with the same stationary distribution; no detailed balance).  EM: device
+ * int64 [nsweeps][count][2], (E, M) after each sweep, or NULL.  ws: device
+ * scratch of mc_dcb_workspace_bytes(geom) bytes (one bit-packed copy of the
+ * lattices, updated in place by the sweeps' launches).  args->rule must be
+ * MC_METROPOLIS (MC_E_LAYOUT otherwise); MC_E_SHAPE for an unsupported L or
+ * tile; MC_E_RANGE for hits outside 1..1000 or (sweep0 + nsweeps) hits >=
+ * 2^55.  Stream-ordered.                                                    */
+size_t mc_dcb_workspace_bytes(const mc_geom *geom);
+int mc_sweep_dcb(mc_ctx *ctx, const mc_geom *geom, void *spins, const mc_sweep_args *args, int32_t tile, int32_t hits,
+                 int64_t *EM, void *ws, size_t ws_bytes, void *stream);
 
 /* E and M of every lattice (lane) as in mc_sweep; EM: device int64
  * [count * lanes][2].  Stream-ordered.                                      */
@@ -300,6 +324,53 @@ int mc_tune_pa(mc_ctx *ctx, const mc_pa_args *args, void *const *pop_spins, void
  * or not increasing, |E| > 2^52 or t >= 2^55.  Nothing is changed on error. */
 int mc_pt_exchange(mc_ctx *ctx, int32_t n_temps, const double *beta, const int64_t *E, int32_t *temp_of,
                    int32_t *replica_at, uint64_t seed, uint64_t round, int64_t *accepted);
+
+/* Parallel tempering on the device (Sec. "Parallel Tempering", Eq. pt):
+ * n_sets independent sets of n_temps replicas of the 2D L x L ferromagnet
+ * (J = 1), replica r of set s is lattice l = s n_temps + r of spins and has
+ * replica id l.  Round t (t = round0 .. round0 + rounds - 1): every replica
+ * runs theta checkerboard Metropolis sweeps (numbers t theta ..) at the
+ * inverse temperature beta[temp_of[l]] it holds; then in every set, with
+ * E the replicas' energies after those sweeps, the pairs of temperatures
+ * (i, i + 1), i = t mod 2, t mod 2 + 2, .., are proposed as in
+ * mc_pt_exchange, the draw being word (i mod 4) of Philox(ctr = (i / 4, s,
+ * t, TAG_EXCHANGE << 24 | t >> 32)) (so set 0 draws exactly as
+ * mc_pt_exchange); acceptance thresholds ceil(exp((beta_i - beta_{i+1}) 4m)
+ * 2^32) for every energy difference 4m are built on the host once per call
+ * (FP64 libm exp).  Temperatures are exchanged, configurations never move.
+ * L as for mc_pa_anneal; 2 <= n_temps <= 1024; n_sets * n_temps <= 65535;
+ * beta strictly increasing, finite, >= 0; theta >= 1.                     */
+typedef struct {
+    int32_t L;
+    int32_t n_temps;
+    int32_t n_sets;
+    const double *beta;   /* host [n_temps]                                    */
+    int32_t theta;        /* sweeps per round                                  */
+    uint64_t seed;
+    uint64_t round0;      /* number of the first round of this call            */
+    int32_t rounds;
+} mc_pt_args;
+
+size_t mc_pt_workspace_bytes(const mc_pt_args *args);
+
+/* spins: device int8 [n_sets * n_temps][L^2], in/out (initialise with mc_init
+ *   and replica0 = 0 for a fresh run).
+ * temp_of, replica_at: host int32 [n_sets][n_temps], in/out: per set the
+ *   replica -> temperature map and its inverse (identity for a fresh run).
+ * accepted: host int64 [n_sets][n_temps - 1], accepted exchanges of each
+ *   pair, added to.
+ * E_at: host int64 [rounds][n_sets][n_temps] or NULL: the energy held at each
+ *   temperature in each round, before that round's exchanges.
+ * ws: device workspace of mc_pt_workspace_bytes(args).  Blocking: the rounds
+ *   run as one captured hipGraph on `stream`, which is synchronised; the
+ *   context keeps the graph, and a call with the same arguments, buffers and
+ *   launch shape launches it again.  A run split over several calls (round0
+ *   advancing, maps and accepted carried over) equals one call.  Errors
+ *   before any device work: MC_E_SHAPE for L, MC_E_RANGE for the counts and
+ *   temperatures, MC_E_INVAL for a NULL pointer or maps that are not inverse
+ *   permutations, MC_E_WORKSPACE.                                          */
+int mc_pt_run(mc_ctx *ctx, const mc_pt_args *args, int8_t *spins, int32_t *temp_of, int32_t *replica_at,
+              int64_t *accepted, int64_t *E_at, void *ws, size_t ws_bytes, void *stream);
 
 /* Launch-shape cache: the tile plans (mc_set_tile_plan) and population-
  * annealing groups (mc_set_pa_group) a context holds, tuned or set, saved to

@@ -58,6 +58,12 @@ class PAArgs(ctypes.Structure):
                 ("nsteps", ctypes.c_int32), ("beta", ctypes.POINTER(ctypes.c_double))]
 
 
+class PTArgs(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("n_temps", ctypes.c_int32), ("n_sets", ctypes.c_int32),
+                ("beta", ctypes.POINTER(ctypes.c_double)), ("theta", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("round0", ctypes.c_uint64), ("rounds", ctypes.c_int32)]
+
+
 PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_int64)
 
 
@@ -104,6 +110,9 @@ _lib_fns = dict(
     mc_sweep=_sig("mc_sweep", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _c.POINTER(SweepArgs), _vp, _vp,
                                          _c.c_size_t, _vp]),
     mc_measure=_sig("mc_measure", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _vp, _vp]),
+    mc_dcb_workspace_bytes=_sig("mc_dcb_workspace_bytes", _c.c_size_t, [_c.POINTER(Geom)]),
+    mc_sweep_dcb=_sig("mc_sweep_dcb", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _c.POINTER(SweepArgs), _c.c_int32,
+                                                 _c.c_int32, _vp, _vp, _c.c_size_t, _vp]),
     mc_sweep_betas=_sig("mc_sweep_betas", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _c.POINTER(SweepArgs),
                                                      _c.POINTER(_c.c_double), _vp, _vp, _c.c_size_t, _vp]),
     mc_set_tile_plan=_sig("mc_set_tile_plan", _c.c_int, [_vp, _c.POINTER(Geom), _c.c_int32, _c.c_int32,
@@ -151,6 +160,10 @@ _lib_fns = dict(
                                                      _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int32),
                                                      _c.POINTER(_c.c_int32), _c.c_uint64, _c.c_uint64,
                                                      _c.POINTER(_c.c_int64)]),
+    mc_pt_workspace_bytes=_sig("mc_pt_workspace_bytes", _c.c_size_t, [_c.POINTER(PTArgs)]),
+    mc_pt_run=_sig("mc_pt_run", _c.c_int, [_vp, _c.POINTER(PTArgs), _vp, _c.POINTER(_c.c_int32),
+                                           _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64),
+                                           _vp, _c.c_size_t, _vp]),
     mc_tuning_save=_sig("mc_tuning_save", _c.c_int, [_vp, _c.c_char_p]),
     mc_tuning_load=_sig("mc_tuning_load", _c.c_int, [_vp, _c.c_char_p]),
     mc_get_pa_group=_sig("mc_get_pa_group", _c.c_int, [_vp, _c.c_int32, _c.POINTER(_c.c_int32)]),
@@ -245,6 +258,19 @@ class Context:
         wsb = 0 if ws is None else ws.numel() * ws.element_size()
         return self._check(_lib.mc_sweep(self._h, ctypes.byref(geom), _ptr(spins), _ptr(J), ctypes.byref(a),
                                          _ptr(EM), _ptr(ws), wsb, _stream(self.device)), "mc_sweep")
+
+    def dcb_workspace_bytes(self, geom):
+        return int(_lib.mc_dcb_workspace_bytes(ctypes.byref(geom)))
+
+    def sweep_dcb(self, geom, spins, beta, seed, nsweeps, tile, hits, sweep0=0, replica0=0, EM=None, ws=None):
+        """Double-checkerboard Metropolis sweeps with `hits` updates per tile
+        (mc_sweep_dcb); ws defaults to a fresh workspace."""
+        if ws is None:
+            ws = torch.empty(max(1, self.dcb_workspace_bytes(geom)), dtype=torch.uint8, device=self.device)
+        a = SweepArgs(METROPOLIS, float(beta), seed, replica0, sweep0, nsweeps)
+        return self._check(_lib.mc_sweep_dcb(self._h, ctypes.byref(geom), _ptr(spins), ctypes.byref(a), tile, hits,
+                                             _ptr(EM), _ptr(ws), ws.numel() * ws.element_size(),
+                                             _stream(self.device)), "mc_sweep_dcb")
 
     def sweep_betas(self, geom, spins, betas, seed, nsweeps, sweep0=0, replica0=0, rule=METROPOLIS, J=None,
                     EM=None, ws=None):
@@ -350,6 +376,53 @@ class Context:
         return self._check(_lib.mc_pt_exchange(self._h, n, p(beta, ctypes.c_double), p(E, ctypes.c_int64),
                                                p(temp_of, ctypes.c_int32), p(replica_at, ctypes.c_int32), seed,
                                                round, p(accepted, ctypes.c_int64)), "mc_pt_exchange")
+
+    @staticmethod
+    def _pt_args(L, beta, n_sets, theta, seed, round0, rounds):
+        import numpy as np
+
+        b = np.ascontiguousarray(beta, dtype=np.float64)
+        a = PTArgs(L, b.size, n_sets, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), theta, seed, round0, rounds)
+        return a, b
+
+    def pt_workspace_bytes(self, L, beta, n_sets, theta, rounds):
+        a, keep = self._pt_args(L, beta, n_sets, theta, 0, 0, rounds)
+        return int(_lib.mc_pt_workspace_bytes(ctypes.byref(a)))
+
+    def pt_state(self, L, n_temps, n_sets, seed, start=HOT):
+        """A fresh tempering run: lattices of replica ids 0 .. n_sets n_temps - 1
+        (device int8 [n_sets n_temps, L^2]), identity maps and zero counts."""
+        import numpy as np
+
+        g = make_geom(2, L, count=n_sets * n_temps)
+        spins = lattice_tensor(g, self.device)
+        self.init(g, spins, start, seed, 0)
+        ident = np.tile(np.arange(n_temps, dtype=np.int32), (n_sets, 1))
+        return dict(spins=spins, temp_of=ident.copy(), replica_at=ident.copy(),
+                    accepted=np.zeros((n_sets, n_temps - 1), dtype=np.int64))
+
+    def pt_run(self, L, beta, theta, seed, state, round0, rounds, record=True, ws=None):
+        """Rounds of parallel tempering (mc_pt_run) on state (from pt_state:
+        device spins, host maps and counts, updated in place); returns E_at
+        ([rounds][n_sets][n_temps] int64) or None."""
+        import numpy as np
+
+        n_sets, n_temps = state["temp_of"].shape
+        a, keep = self._pt_args(L, beta, n_sets, theta, seed, round0, rounds)
+        need = int(_lib.mc_pt_workspace_bytes(ctypes.byref(a)))
+        if ws is None:
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=self.device)
+        E_at = np.zeros((max(rounds, 1), n_sets, n_temps), dtype=np.int64) if record else None
+        p = lambda x, t: None if x is None else x.ctypes.data_as(ctypes.POINTER(t))
+        for k, dt in (("temp_of", np.int32), ("replica_at", np.int32), ("accepted", np.int64)):
+            x = state[k]
+            if not (isinstance(x, np.ndarray) and x.dtype == dt and x.flags.c_contiguous):
+                raise TypeError("state[%r] must be a contiguous %s array" % (k, dt.__name__))
+        self._check(_lib.mc_pt_run(self._h, ctypes.byref(a), _ptr(state["spins"]), p(state["temp_of"], ctypes.c_int32),
+                                   p(state["replica_at"], ctypes.c_int32), p(state["accepted"], ctypes.c_int64),
+                                   p(E_at, ctypes.c_int64), _ptr(ws), ws.numel() * ws.element_size(),
+                                   _stream(self.device)), "mc_pt_run")
+        return None if E_at is None else E_at[:rounds]
 
     def save_launch_shapes(self, path):
         """Write the context's tile plans and PA groups to a text file."""

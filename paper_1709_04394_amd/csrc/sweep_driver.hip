@@ -396,3 +396,69 @@ int mc_tune_sweep_rule(mc_ctx *ctx, const mc_geom *geom, int32_t rule, void *scr
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Double-checkerboard sweeps with k hits per tile (a different Markov chain
+// from mc_sweep's): the caller's int8 lattices are packed into the workspace
+// once, every sweep is two in-place launches (one per coarse colour of the
+// tiles), and the last step unpacks them.
+extern "C" {
+
+size_t mc_dcb_workspace_bytes(const mc_geom *geom)
+{
+    if (!geom || check_geom(nullptr, geom, true) != MC_OK) return 0;
+    if (geom->dims != 2 || geom->layout != MC_INT8 || geom->Lx != geom->Ly || geom->Lx % 64 ||
+        geom->Lx > 16384)
+        return 0;
+    return packed_bytes(to_geom(geom));
+}
+
+int mc_sweep_dcb(mc_ctx *ctx, const mc_geom *geom, void *spins, const mc_sweep_args *args, int32_t tile,
+                 int32_t hits, int64_t *EM, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx) return MC_E_INVAL;
+    int rc = check_sweep_args(ctx, geom, spins, args);
+    if (rc) return rc;
+    if (geom->dims != 2 || geom->layout != MC_INT8)
+        return fail(ctx, MC_E_LAYOUT, "the double checkerboard takes 2D int8 lattices");
+    if (args->rule != MC_METROPOLIS) return fail(ctx, MC_E_LAYOUT, "the double checkerboard runs Metropolis updates");
+    const int L = geom->Lx;
+    if (geom->Ly != L || L % 64 || L > 16384)
+        return fail(ctx, MC_E_SHAPE, "the double checkerboard takes L x L lattices, L a multiple of 64 up to 16384");
+    if (tile != 64 && tile != 128 && tile != 256 && tile != 512)
+        return fail(ctx, MC_E_SHAPE, "tile must be 64, 128, 256 or 512 (got %d)", tile);
+    if (L % tile || ((L / tile) & 1))
+        return fail(ctx, MC_E_SHAPE, "L / tile must be an even integer (L = %d, tile = %d)", L, tile);
+    if (hits < 1 || hits > 1000) return fail(ctx, MC_E_RANGE, "hits must be 1..1000 (got %d)", hits);
+    if ((args->sweep0 + (uint64_t)args->nsweeps) * (uint64_t)hits >= (1ull << 55))
+        return fail(ctx, MC_E_RANGE, "sweep numbers times hits must stay below 2^55");
+    const Geom g = to_geom(geom);
+    const size_t need = packed_bytes(g);
+    if (!ws || ws_bytes < need) return fail(ctx, MC_E_WORKSPACE, "workspace needs %zu bytes", need);
+    if (args->nsweeps == 0) return MC_OK;
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    SweepCall c;
+    c.g = g;
+    c.J = nullptr;
+    c.rule = MC_METROPOLIS;
+    c.seed_lo = (uint32_t)args->seed;
+    c.seed_hi = (uint32_t)(args->seed >> 32);
+    c.replica0 = args->replica0;
+    c.tab = build_tables(args->beta);
+    c.per_lattice = 0;
+    c.tabs = nullptr;
+    // conversions between int8 and packed rows: band launches of no sweeps
+    const TilePlan conv = default_tile_plan(g);
+    const int H = std::min(conv.H, g.Ly);
+    hipError_t e = EM ? launch_fill_i64(EM, 2 * (int64_t)args->nsweeps * g.count, 0, s) : hipSuccess;
+    if (e == hipSuccess) e = launch_tile2d(c, spins, 0, ws, 1, 0, 0, H, conv.threads, nullptr, 0, 0, s);
+    for (int t = 0; t < args->nsweeps && e == hipSuccess; ++t)
+        for (int P = 0; P < 2 && e == hipSuccess; ++P)
+            e = launch_dcb_phase((uint32_t *)ws, L, tile, g.count, P, hits, c.replica0, args->sweep0 + (uint64_t)t,
+                                 c.seed_lo, c.seed_hi, c.tab, EM ? EM + 2 * (int64_t)t * g.count : nullptr, s);
+    if (e == hipSuccess) e = launch_tile2d(c, ws, 1, spins, 0, 0, 0, H, conv.threads, nullptr, 0, 0, s);
+    return device_check(ctx, e, "mc_sweep_dcb");
+}
+
+}  // extern "C"

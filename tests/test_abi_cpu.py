@@ -271,3 +271,34 @@ def test_import_fails_loudly_without_the_library(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], cwd=str(tmp_path), capture_output=True, text=True, timeout=300,
                        env=dict(os.environ, PYTHONPATH=str(tmp_path)))
     assert r.returncode != 0 and "ImportError" in r.stderr and "libmcspin.so is not built" in r.stderr, r.stderr
+
+
+def test_dcb_argument_checks():
+    """mc_sweep_dcb validates before any device work (no GPU needed)."""
+    h = ctypes.c_void_p()
+    assert mcs._lib.mc_ctx_create(ctypes.byref(h), 0) == 0
+    try:
+        fake = ctypes.c_void_p(1)
+
+        def call(g, tile=128, hits=2, rule=0, nsw=3, wsb=None, sweep0=0):
+            a = mcs.SweepArgs(rule, 0.4, 1, 0, sweep0, nsw)
+            wsb = mcs._lib.mc_dcb_workspace_bytes(ctypes.byref(g)) if wsb is None else wsb
+            return mcs._lib.mc_sweep_dcb(h, ctypes.byref(g), fake, ctypes.byref(a), tile, hits, None, fake, wsb, None)
+
+        g = mcs.make_geom(2, 512, count=2)
+        assert mcs._lib.mc_dcb_workspace_bytes(ctypes.byref(g)) == 2 * 512 * 512 // 8
+        assert mcs._lib.mc_dcb_workspace_bytes(ctypes.byref(mcs.make_geom(2, (512, 256)))) == 0
+        assert mcs._lib.mc_dcb_workspace_bytes(ctypes.byref(mcs.make_geom(3, 64))) == 0
+        assert call(g, rule=mcs.HEATBATH) == mcs.MC_E_LAYOUT
+        assert call(mcs.make_geom(3, 64)) == mcs.MC_E_LAYOUT
+        assert call(mcs.make_geom(2, 512, layout=mcs.MSC64)) == mcs.MC_E_LAYOUT
+        assert call(mcs.make_geom(2, (512, 256))) == mcs.MC_E_SHAPE
+        assert call(mcs.make_geom(2, 96)) == mcs.MC_E_SHAPE
+        assert call(g, tile=96) == mcs.MC_E_SHAPE
+        assert call(mcs.make_geom(2, 384), tile=128) == mcs.MC_E_SHAPE  # 3 tiles per side: odd
+        assert call(g, hits=0) == mcs.MC_E_RANGE and call(g, hits=1001) == mcs.MC_E_RANGE
+        assert call(g, hits=1000, sweep0=(1 << 55) // 1000) == mcs.MC_E_RANGE
+        assert call(g, wsb=2 * 512 * 512 // 8 - 1) == mcs.MC_E_WORKSPACE
+        assert call(g, nsw=0) == 0  # nothing to do: no device work
+    finally:
+        mcs._lib.mc_ctx_destroy(h)

@@ -74,3 +74,43 @@ def test_binding_checks_types(ctx):
     with pytest.raises(ValueError):
         ctx.pt_exchange([0.1, 0.2], [0, 0], np.arange(2, dtype=np.int32), np.arange(2, dtype=np.int32), 1, 0,
                         np.zeros(2, np.int64))
+
+
+def _pt_args(L=16, beta=(0.3, 0.4, 0.5), n_sets=2, theta=2, rounds=5, round0=0):
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    a = mcs.PTArgs(L, b.size, n_sets, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), theta, 7, round0, rounds)
+    return a, b
+
+
+def test_pt_run_workspace_and_argument_errors(ctx):
+    """mc_pt_run checks everything before any device work (no GPU needed):
+    the workspace formula, extents, counts, temperatures and maps."""
+    a, keep = _pt_args()
+    nb = mcs._lib.mc_pt_workspace_bytes(ctypes.byref(a))
+    # thresholds, exchange table (2 pairs x (N + 1) entries), maps, energies,
+    # counts and the recorded energies, each rounded up to 256 B
+    up = lambda b: (b + 255) // 256 * 256
+    count, N = 6, 256
+    assert nb == up(3 * 2 * 8) + up(2 * (N + 1) * 8) + 3 * up(count * 4) + up(2 * 2 * 8) + up(5 * count * 8)
+    t = np.tile(np.arange(3, dtype=np.int32), (2, 1))
+    r, acc = t.copy(), np.zeros((2, 2), dtype=np.int64)
+    p = lambda x, ty: x.ctypes.data_as(ctypes.POINTER(ty))
+    fake = ctypes.c_void_p(1)
+
+    def call(args, tt=t, rr=r, ws=fake, wsb=nb):
+        return mcs._lib.mc_pt_run(ctx._h, ctypes.byref(args), fake, p(tt, ctypes.c_int32), p(rr, ctypes.c_int32),
+                                  p(acc, ctypes.c_int64), None, ws, wsb, None)
+
+    assert call(_pt_args(L=12)[0]) == mcs.MC_E_SHAPE
+    assert call(_pt_args(beta=(0.3,))[0]) == mcs.MC_E_RANGE
+    assert call(_pt_args(beta=(0.3, 0.3, 0.5))[0]) == mcs.MC_E_RANGE
+    assert call(_pt_args(beta=(0.3, float("nan"), 0.5))[0]) == mcs.MC_E_RANGE
+    assert call(_pt_args(theta=0)[0]) == mcs.MC_E_RANGE
+    assert call(_pt_args(n_sets=0)[0]) == mcs.MC_E_RANGE
+    assert call(_pt_args(n_sets=30000)[0]) == mcs.MC_E_RANGE
+    bad = t.copy()
+    bad[1] = [0, 2, 1]  # temp_of of set 1 no longer inverse to replica_at
+    assert call(a, tt=bad) == mcs.MC_E_INVAL
+    assert call(a, wsb=nb - 1) == mcs.MC_E_WORKSPACE
+    assert call(a, ws=None) == mcs.MC_E_WORKSPACE
+    assert np.array_equal(t, np.tile(np.arange(3), (2, 1))) and not acc.any()  # nothing changed
