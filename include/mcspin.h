@@ -11,7 +11,8 @@
  *     point to memory of the context's device; "host" pointers to host memory.
  *   - The caller owns every buffer.  The library never allocates or frees
  *     device memory inside a call; scratch space comes from caller workspaces
- *     whose size the matching *_workspace_bytes() call reports.
+ *     whose size the matching *_workspace_bytes() call reports (or, for
+ *     mc_sweep_noalloc, from a fixed device array of the library).
  *   - Return value: 0 on success, a negative mc_status otherwise.  Arguments
  *     are checked in full before any device work is enqueued, so a failing call
  *     has no side effect.  mc_strerror() names a code, mc_ctx_last_error() gives
@@ -154,6 +155,26 @@ int mc_sweep(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *J, con
  * them (taller bands, less redone halo).                                   */
 int mc_sweep_betas(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *J, const mc_sweep_args *args,
                    const double *betas, int64_t *EM, void *ws, size_t ws_bytes, void *stream);
+
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): mc_sweep without a
+ * workspace argument.  The scratch the fused kernels need (the size
+ * mc_sweep_workspace_bytes reports) comes from a device array of the library
+ * of mc_static_scratch_bytes() bytes (16 MiB), one per device, held until
+ * the process ends; its address is looked up once per device on the first
+ * call.  The call allocates nothing: no hipMalloc, hipFree or allocating
+ * library routine.  Results are those of mc_sweep with a large enough
+ * workspace.  Every call on a device shares that device's array and leaves
+ * it holding its own intermediate lattices, so calls that overlap in time on
+ * one device (different streams or host threads) race and must not be made;
+ * calls in one stream are fine.  Errors: those of mc_sweep; MC_E_RANGE,
+ * before any device work, when the geometry's fused scratch is larger than
+ * the array (e.g. more than four 4096^2 lattices, or a 2D lattice above
+ * 2^26 sites); geometries that need no scratch run as mc_sweep does without
+ * a workspace.  Stream-ordered.                                            */
+size_t mc_static_scratch_bytes(void);
+int mc_sweep_noalloc(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *J, const mc_sweep_args *args,
+                     int64_t *EM, void *stream);
 
 /* Double-checkerboard Metropolis sweeps with `hits` updates per tile load
  * (Sec. "Checkerboard scheme": the two-level "double checkerboard" of the

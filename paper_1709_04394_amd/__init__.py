@@ -110,6 +110,9 @@ _lib_fns = dict(
     mc_sweep=_sig("mc_sweep", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _c.POINTER(SweepArgs), _vp, _vp,
                                          _c.c_size_t, _vp]),
     mc_measure=_sig("mc_measure", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _vp, _vp]),
+    mc_static_scratch_bytes=_sig("mc_static_scratch_bytes", _c.c_size_t, []),
+    mc_sweep_noalloc=_sig("mc_sweep_noalloc", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _c.POINTER(SweepArgs), _vp,
+                                                         _vp]),
     mc_dcb_workspace_bytes=_sig("mc_dcb_workspace_bytes", _c.c_size_t, [_c.POINTER(Geom)]),
     mc_sweep_dcb=_sig("mc_sweep_dcb", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _c.POINTER(SweepArgs), _c.c_int32,
                                                  _c.c_int32, _vp, _vp, _c.c_size_t, _vp]),
@@ -258,6 +261,14 @@ class Context:
         wsb = 0 if ws is None else ws.numel() * ws.element_size()
         return self._check(_lib.mc_sweep(self._h, ctypes.byref(geom), _ptr(spins), _ptr(J), ctypes.byref(a),
                                          _ptr(EM), _ptr(ws), wsb, _stream(self.device)), "mc_sweep")
+
+    def sweep_noalloc(self, geom, spins, beta, seed, nsweeps, sweep0=0, replica0=0, rule=METROPOLIS, J=None,
+                      EM=None):
+        """mc_sweep_noalloc: the sweep with the library's fixed device scratch
+        instead of a workspace (allocates nothing)."""
+        a = SweepArgs(rule, float(beta), seed, replica0, sweep0, nsweeps)
+        return self._check(_lib.mc_sweep_noalloc(self._h, ctypes.byref(geom), _ptr(spins), _ptr(J), ctypes.byref(a),
+                                                 _ptr(EM), _stream(self.device)), "mc_sweep_noalloc")
 
     def dcb_workspace_bytes(self, geom):
         return int(_lib.mc_dcb_workspace_bytes(ctypes.byref(geom)))

@@ -17,6 +17,9 @@ namespace mcs {
 // Launch shape of the fused sweeps: band height (2D) or tile side in y and z
 // (3D), sweeps per launch and threads per workgroup.  Any choice gives the
 // same results.
+// Size of the device array behind mc_sweep_noalloc (one copy per device).
+constexpr size_t kStaticScratchBytes = (size_t)16 << 20;
+
 struct TilePlan {
     int H = 16;
     int K = 2;
