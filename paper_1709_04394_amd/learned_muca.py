@@ -121,32 +121,53 @@ def compare(ctx, L, params, seed=None, prod_sweeps=0, **kw):
 # of thousands of sweeps per walker; separate runs (each from its own walker
 # start and burn-in, different seeds) add their histograms.
 
-def production(ctx, L, lnW, seed, burn, sweeps, walkers=WALKERS, chunk=1000, label=""):
+def production(ctx, L, lnW, seed, burn, sweeps, walkers=WALKERS, chunk=1000, label="", checkpoints=None):
     """Recorded histogram of `sweeps` multicanonical sweeps per walker at fixed
     weights lnW, after a stratified walker start and `burn` unrecorded sweeps;
     sweeps are numbered from 0 over burn-in and production.  Returns the int64
-    histogram over the window levels."""
+    histogram over the window levels, or, with checkpoints (increasing counts
+    of recorded sweeps, the last = sweeps), the cumulative histogram at each
+    checkpoint as an array [len(checkpoints)][levels].  The walker count is
+    free here: production runs at fixed weights, so more walkers (up to the
+    16384 whose lattices fill every compute unit once at L = 128) give more
+    statistics per sweep at about the same wall time."""
     from . import MUCA_STRATIFIED
 
+    cps = [sweeps] if checkpoints is None else list(checkpoints)
+    if sorted(cps) != cps or cps[-1] != sweeps or cps[0] < 1:
+        raise ValueError("checkpoints must increase and end at sweeps")
     spins, E = ctx.muca_start(L, walkers, seed, start=MUCA_STRATIFIED)
     ws = ctx.muca_workspace(L, walkers)
     H = torch.zeros(L * L // 2 + 1, dtype=torch.int64, device=ctx.device)
     t0 = time.perf_counter()
     last, sw = t0, 0
-    for rec, n in ((False, burn), (True, sweeps)):
-        done = 0
-        while done < n:
-            k = min(chunk, n - done)
-            ctx.muca_sweeps(L, spins, E, lnW, seed, sw, k, rec, H=H if rec else None, ws=ws)
+    out = []
+    done = 0
+    while done < burn:
+        k = min(chunk, burn - done)
+        ctx.muca_sweeps(L, spins, E, lnW, seed, sw, k, False, ws=ws)
+        done += k
+        sw += k
+        torch.cuda.synchronize()
+        now = time.perf_counter()
+        if now - last > 20:
+            last = now
+            print("%s seed %d: burn-in %d/%d, %.0f s" % (label, seed, done, burn, now - t0), file=sys.stderr, flush=True)
+    done = 0
+    for cp in cps:
+        while done < cp:
+            k = min(chunk, cp - done)
+            ctx.muca_sweeps(L, spins, E, lnW, seed, sw, k, True, H=H, ws=ws)
             done += k
             sw += k
             torch.cuda.synchronize()
             now = time.perf_counter()
             if now - last > 20:
                 last = now
-                print("%s seed %d: %s %d/%d, %.0f s" % (label, seed, "production" if rec else "burn-in", done, n,
-                                                       now - t0), file=sys.stderr, flush=True)
-    return H.cpu().numpy()
+                print("%s seed %d: production %d/%d, %.0f s" % (label, seed, done, sweeps, now - t0),
+                      file=sys.stderr, flush=True)
+        out.append(H.cpu().numpy())
+    return out[-1] if checkpoints is None else np.stack(out)
 
 
 def lng_errors(H, lnW, lng_exact):
@@ -165,13 +186,33 @@ def lng_errors(H, lnW, lng_exact):
     return float(np.max(np.abs(a + c - b))), float((d.max() - d.min()) / 2)
 
 
+def arm_summary(r):
+    """The sweep counts of one arm's run to a flat histogram: multicanonical
+    sweeps per walker, plus the walker preparation (the same for both arms)."""
+    return {"converged": bool(r["converged"]), "iterations": int(r["iterations"]),
+            "sweeps_per_walker": int(r["sweeps_per_walker"]),
+            "prep_sweeps_per_walker": int(r["prep_sweeps_per_walker"]),
+            "sweeps_per_walker_incl_prep": int(r["sweeps_per_walker"]) + int(r["prep_sweeps_per_walker"]),
+            "seconds": round(float(r["seconds"]), 2), "final_min_over_max": float(r["min_over_max"])}
+
+
 def main(argv=None):
-    """Stages of the L = 128 comparison run to the accuracy target:
-      converge --L 128 --out DIR        training sizes, MLP, both arms to a flat
-                                        histogram; DIR/weights.npz, DIR/converge.json
-      produce --dir DIR --arm A --seed S --burn B --sweeps P
-                                        one production run; DIR/H_A_S.npy
-      score --dir DIR --exact FILE      errors per run and per arm (runs summed)"""
+    """Stages of the learned-vs-plain comparison at one size:
+      converge --L L --seeds S,.. --out DIR
+            training sizes and the MLP (once), then both arms to a flat
+            histogram for every seed: DIR/lnW_<arm>_<S>.npy, DIR/lnW_init.npy,
+            DIR/converge.json
+      produce --dir DIR --arm A --seed S --pseed P --walkers W --burn B
+              --checkpoints C1,..,Cn
+            production at the arm's converged weights of seed S (walker seed
+            P): cumulative histograms after C1 .. Cn sweeps,
+            DIR/prod_<arm>_<S>_<P>.npy
+      score --dir DIR --exact FILE [--target 0.01]
+            max |ln g error| of every production checkpoint, after matching
+            the normalisations by log-sum-exp over the window levels with
+            states (the accuracy metric) and after the best constant; the
+            walker-sweeps at the first checkpoint within the target; sweeps
+            to flat per arm over the seeds"""
     import argparse
     import glob
     import json
@@ -180,42 +221,45 @@ def main(argv=None):
     p = argparse.ArgumentParser(prog="python -m paper_1709_04394_amd.learned_muca")
     sub = p.add_subparsers(dest="stage", required=True)
     c = sub.add_parser("converge")
-    c.add_argument("--L", type=int, default=128)
+    c.add_argument("--L", type=int, required=True)
+    c.add_argument("--seeds", required=True)
     c.add_argument("--out", required=True)
     q = sub.add_parser("produce")
     q.add_argument("--dir", required=True)
     q.add_argument("--arm", choices=("plain", "learned"), required=True)
     q.add_argument("--seed", type=int, required=True)
+    q.add_argument("--pseed", type=int, required=True)
+    q.add_argument("--walkers", type=int, default=16384)
     q.add_argument("--burn", type=int, default=20000)
-    q.add_argument("--sweeps", type=int, required=True)
-    q.add_argument("--refined", action="store_true",
-                   help="run at ln W = -ln g estimated from the arm's earlier runs (summed), saved as "
-                        "DIR/weights_refined_A.npy; the histogram goes to DIR/HR_A_S.npy")
+    q.add_argument("--checkpoints", required=True)
     s = sub.add_parser("score")
     s.add_argument("--dir", required=True)
     s.add_argument("--exact", required=True, help="stored exact ln g over the window levels (text)")
+    s.add_argument("--target", type=float, default=0.01)
     a = p.parse_args(argv)
 
     if a.stage == "score":
-        w = np.load(os.path.join(a.dir, "weights.npz"))
         conv = json.load(open(os.path.join(a.dir, "converge.json")))
         ex = np.loadtxt(a.exact)
-        out = {}
+        out = {"L": conv["L"], "target": a.target, "metric": "max |ln g_est - ln g_exact| over the window levels "
+               "with states, normalisations matched by log-sum-exp", "arms": {}}
         for arm in ("plain", "learned"):
-            files = sorted(glob.glob(os.path.join(a.dir, "H_%s_*.npy" % arm)))
-            if not files:
-                continue
-            runs = {os.path.basename(f)[:-4]: lng_errors(np.load(f), w["lnW_" + arm], ex) for f in files}
-            Hs = sum(np.load(f) for f in files)
-            lse, best = lng_errors(Hs, w["lnW_" + arm], ex)
-            out[arm] = dict(conv[arm], runs=runs, production_records=int(Hs.sum()),
-                            max_abs_lng_error=lse, max_abs_lng_error_best_constant=best)
-            rf = os.path.join(a.dir, "weights_refined_%s.npy" % arm)
-            rfiles = sorted(glob.glob(os.path.join(a.dir, "HR_%s_*.npy" % arm)))
-            if rfiles and os.path.exists(rf):
-                lnWr = np.load(rf)
-                out[arm]["refined_runs"] = {os.path.basename(f)[:-4]: lng_errors(np.load(f), lnWr, ex)
-                                            for f in rfiles}
+            seeds = conv["seeds"]
+            flat = [conv["runs"][str(sd)][arm]["sweeps_per_walker_incl_prep"] for sd in seeds]
+            row = {"sweeps_to_flat_incl_prep": flat, "mean": float(np.mean(flat)),
+                   "min": int(min(flat)), "max": int(max(flat)), "production": {}}
+            for f in sorted(glob.glob(os.path.join(a.dir, "prod_%s_*.npy" % arm))):
+                meta = json.load(open(f[:-4] + ".json"))
+                lnW = np.load(os.path.join(a.dir, "lnW_%s_%d.npy" % (arm, meta["seed"])))
+                Hs = np.load(f)
+                errs = [lng_errors(H, lnW, ex) for H in Hs]
+                reach = [cp for cp, e in zip(meta["checkpoints"], errs) if e[0] <= a.target]
+                row["production"][os.path.basename(f)[:-4]] = dict(
+                    meta, errors_logsumexp=[e[0] for e in errs], errors_best_constant=[e[1] for e in errs],
+                    walker_sweeps_to_target=(reach[0] * meta["walkers"]) if reach else None)
+            out["arms"][arm] = row
+        pl, le = out["arms"]["plain"]["mean"], out["arms"]["learned"]["mean"]
+        out["mean_sweeps_to_flat_ratio_learned_over_plain"] = le / pl
         print(json.dumps(out, indent=1))
         return
 
@@ -224,30 +268,32 @@ def main(argv=None):
     ctx = Context(0)
     if a.stage == "converge":
         os.makedirs(a.out, exist_ok=True)
+        seeds = [int(x) for x in a.seeds.split(",")]
         lnW_by_L, _ = training_weights(ctx)
         params, log = train_network(ctx, lnW_by_L)
-        r = compare(ctx, a.L, params, prod_sweeps=0)
-        conv = {arm: {k: (bool(r[arm][k]) if k == "converged" else float(r[arm][k]))
-                      for k in ("iterations", "sweeps_per_walker", "total_sweeps", "seconds", "min_over_max",
-                                "converged")} for arm in ("plain", "learned")}
-        conv["mlp_loss"] = [float(log[0]), float(log[-1])]
-        np.savez(os.path.join(a.out, "weights.npz"), lnW_plain=r["plain"]["lnW"], lnW_learned=r["learned"]["lnW"],
-                 lnW_init=r["lnW_init"], L=a.L)
-        json.dump(conv, open(os.path.join(a.out, "converge.json"), "w"))
-        print(json.dumps(conv), flush=True)
+        conv = {"L": a.L, "seeds": seeds, "mlp_loss": [float(log[0]), float(log[-1])], "runs": {}}
+        for sd in seeds:
+            r = compare(ctx, a.L, params, seed=sd, prod_sweeps=0)
+            conv["runs"][str(sd)] = {arm: arm_summary(r[arm]) for arm in ("plain", "learned")}
+            conv["runs"][str(sd)]["learned"]["fallback"] = bool(r["learned"]["fallback"])
+            for arm in ("plain", "learned"):
+                np.save(os.path.join(a.out, "lnW_%s_%d.npy" % (arm, sd)), r[arm]["lnW"])
+            np.save(os.path.join(a.out, "lnW_init.npy"), r["lnW_init"])
+            json.dump(conv, open(os.path.join(a.out, "converge.json"), "w"), indent=1)
+            print(json.dumps({"seed": sd, "runs": conv["runs"][str(sd)]}), flush=True)
     else:
-        w = np.load(os.path.join(a.dir, "weights.npz"))
-        L = int(w["L"])
-        lnW = w["lnW_" + a.arm]
-        if a.refined:
-            files = sorted(glob.glob(os.path.join(a.dir, "H_%s_*.npy" % a.arm)))
-            if not files:
-                raise SystemExit("no earlier runs of arm %s in %s" % (a.arm, a.dir))
-            lnW = refined_weights(ctx, L, lnW, sum(np.load(f) for f in files))
-            np.save(os.path.join(a.dir, "weights_refined_%s.npy" % a.arm), lnW)
-        H = production(ctx, L, lnW, a.seed, a.burn, a.sweeps, label=a.arm)
-        np.save(os.path.join(a.dir, "%s_%s_%d.npy" % ("HR" if a.refined else "H", a.arm, a.seed)), H)
-        print(json.dumps({"arm": a.arm, "seed": a.seed, "burn": a.burn, "sweeps": a.sweeps}), flush=True)
+        conv = json.load(open(os.path.join(a.dir, "converge.json")))
+        L = int(conv["L"])
+        lnW = np.load(os.path.join(a.dir, "lnW_%s_%d.npy" % (a.arm, a.seed)))
+        cps = [int(x) for x in a.checkpoints.split(",")]
+        t0 = time.perf_counter()
+        Hs = production(ctx, L, lnW, a.pseed, a.burn, cps[-1], walkers=a.walkers, label=a.arm, checkpoints=cps)
+        base = os.path.join(a.dir, "prod_%s_%d_%d" % (a.arm, a.seed, a.pseed))
+        np.save(base + ".npy", Hs)
+        meta = {"arm": a.arm, "seed": a.seed, "pseed": a.pseed, "walkers": a.walkers, "burn": a.burn,
+                "checkpoints": cps, "seconds": round(time.perf_counter() - t0, 1)}
+        json.dump(meta, open(base + ".json", "w"))
+        print(json.dumps(meta), flush=True)
 
 
 if __name__ == "__main__":

@@ -50,23 +50,34 @@ def test_empty_level_is_infinite():
 
 
 def test_score_stage_end_to_end(tmp_path, capsys):
-    # the command-line score stage on synthetic files: two runs of one arm whose
-    # summed histogram reproduces the exact ln g up to a constant, one that
-    # does not
+    # the command-line score stage on synthetic files: converged weights of
+    # two seeds per arm, sweeps to flat per seed, and production checkpoints
+    # whose histograms reproduce the exact ln g up to a constant (plain) or
+    # only after the second checkpoint (learned: the first one has ten levels
+    # doubled, an error of ln 2 / 2 after the best constant)
     import json
 
     ex, H, lnW, m = _setup()
-    np.savez(tmp_path / "weights.npz", lnW_plain=lnW, lnW_learned=lnW, lnW_init=lnW, L=16)
-    conv = {arm: {"iterations": 1.0, "sweeps_per_walker": 10.0, "total_sweeps": 10.0, "seconds": 0.0,
-                  "min_over_max": 1.0, "converged": True} for arm in ("plain", "learned")}
+    conv = {"L": 16, "seeds": [1, 2], "mlp_loss": [1.0, 0.1], "runs": {}}
+    for sd, (fp, fl) in ((1, (900, 500)), (2, (1100, 700))):
+        conv["runs"][str(sd)] = {
+            "plain": {"sweeps_per_walker_incl_prep": fp}, "learned": {"sweeps_per_walker_incl_prep": fl}}
+        for arm in ("plain", "learned"):
+            np.save(tmp_path / ("lnW_%s_%d.npy" % (arm, sd)), lnW)
     (tmp_path / "converge.json").write_text(json.dumps(conv))
-    np.save(tmp_path / "H_plain_1.npy", H)
-    np.save(tmp_path / "H_plain_2.npy", 2 * H)
     Hb = H.copy()
     Hb[np.flatnonzero(m)[:10]] *= 2
-    np.save(tmp_path / "H_learned_1.npy", Hb)
-    lm.main(["score", "--dir", str(tmp_path), "--exact", GOLD])
+    for arm, hs in (("plain", [H, 3 * H]), ("learned", [Hb, 2 * Hb + 2 * H])):
+        base = tmp_path / ("prod_%s_1_7" % arm)
+        np.save(str(base) + ".npy", np.stack(hs))
+        (tmp_path / ("prod_%s_1_7.json" % arm)).write_text(json.dumps(
+            {"arm": arm, "seed": 1, "pseed": 7, "walkers": 64, "burn": 0, "checkpoints": [10, 30]}))
+    lm.main(["score", "--dir", str(tmp_path), "--exact", GOLD, "--target", "0.01"])
     out = json.loads(capsys.readouterr().out)
-    assert out["plain"]["max_abs_lng_error_best_constant"] < 1e-9
-    assert set(out["plain"]["runs"]) == {"H_plain_1", "H_plain_2"}
-    assert abs(out["learned"]["max_abs_lng_error_best_constant"] - np.log(2) / 2) < 1e-9
+    pl, le = out["arms"]["plain"], out["arms"]["learned"]
+    assert pl["sweeps_to_flat_incl_prep"] == [900, 1100] and pl["mean"] == 1000
+    assert le["mean"] == 600 and abs(out["mean_sweeps_to_flat_ratio_learned_over_plain"] - 0.6) < 1e-12
+    pp, lp = pl["production"]["prod_plain_1_7"], le["production"]["prod_learned_1_7"]
+    assert max(pp["errors_best_constant"]) < 1e-9 and pp["walker_sweeps_to_target"] == 10 * 64
+    assert abs(lp["errors_best_constant"][0] - np.log(2) / 2) < 1e-9
+    assert lp["errors_best_constant"][1] > 1e-3 and lp["walker_sweeps_to_target"] is None
