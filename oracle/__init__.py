@@ -68,6 +68,7 @@ def lib():
         L.orc_heatbath_table.argtypes = [ctypes.c_double, ctypes.c_int, u8p]
         L.orc_init.argtypes = [ctypes.c_int] * 4 + [u8p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32]
         L.orc_couplings.argtypes = [ctypes.c_int] * 4 + [u8p, ctypes.c_uint64]
+        L.orc_couplings_of.argtypes = [ctypes.c_int] * 4 + [u8p, ctypes.c_uint64, ctypes.c_uint32]
         L.orc_measure.argtypes = [ctypes.c_int] * 4 + [u8p, u8p, u8p, u8p]
         L.orc_measure.restype = None
         L.orc_sweep.argtypes = [ctypes.c_int] * 4 + [u8p, u8p, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
@@ -155,10 +156,15 @@ def init(dims, L, start, seed, replica=0):
     return s
 
 
-def couplings(dims, L, seed):
+def couplings(dims, L, seed, realisation=0):
+    """Bimodal couplings of disorder realisation `realisation` (int8
+    [dims][N], +1 / -1 with p = 1/2)."""
     Lx, Ly, Lz = _shape(dims, L)
     J = np.zeros(dims * Lx * Ly * Lz, dtype=np.int8)
-    _check(lib().orc_couplings(dims, Lx, Ly, Lz, _p(J), seed), "couplings")
+    if realisation == 0:
+        _check(lib().orc_couplings(dims, Lx, Ly, Lz, _p(J), seed), "couplings")
+    else:
+        _check(lib().orc_couplings_of(dims, Lx, Ly, Lz, _p(J), seed, realisation), "couplings")
     return J
 
 

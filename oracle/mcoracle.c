@@ -231,14 +231,21 @@ int orc_init(int dims, int Lx, int Ly, int Lz, int8_t *s, int start, uint64_t se
     return 0;
 }
 
-/* Bimodal couplings J = +-1 with p = 1/2, one per bond (site, direction). */
-int orc_couplings(int dims, int Lx, int Ly, int Lz, int8_t *J, uint64_t seed)
+/* Bimodal couplings J = +-1 with p = 1/2, one per bond (site, direction), of
+ * disorder realisation `realisation` (counter word 1; realisation 0 is the
+ * single realisation of the plain spin-glass runs).                          */
+int orc_couplings_of(int dims, int Lx, int Ly, int Lz, int8_t *J, uint64_t seed, uint32_t realisation)
 {
     orc_geom g = mkgeom(dims, Lx, Ly, Lz);
     if (!geom_ok(&g)) return -1;
     for (int64_t b = 0; b < (int64_t)dims * g.N; ++b)
-        J[b] = orc_draw_byte(seed, ORC_TAG_COUPLING, (uint32_t)b, 0, 0, 0) < 128u ? 1 : -1;
+        J[b] = orc_draw_byte(seed, ORC_TAG_COUPLING, (uint32_t)b, realisation, 0, 0) < 128u ? 1 : -1;
     return 0;
+}
+
+int orc_couplings(int dims, int Lx, int Ly, int Lz, int8_t *J, uint64_t seed)
+{
+    return orc_couplings_of(dims, Lx, Ly, Lz, J, seed, 0);
 }
 
 /* E = -sum over bonds J_ij s_i s_j (each bond once), M = sum s_i. */

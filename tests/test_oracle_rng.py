@@ -172,3 +172,26 @@ def test_weyl_increments_follow_their_definition_in_both_sources():
     got_orc = [int(re.search(r"#define ORC_PHILOX_%s (0x[0-9A-Fa-f]+)u" % n, orc).group(1), 16) for n in ("W0", "W1")]
     got_lib = [int(re.search(r"kPhilox%s = (0x[0-9A-Fa-f]+)u" % n, lib).group(1), 16) for n in ("W0", "W1")]
     assert got_orc == [w0, w1] and got_lib == [w0, w1]
+
+
+@pytest.mark.parametrize("realisation", [0, 1, 63, 4095])
+def test_couplings_of_a_realisation_follow_the_documented_counter_layout(realisation):
+    # bond b = d N + i of realisation k is +1 iff the gathered byte (b mod 16)
+    # of Philox(ctr = (b / 16, k, 0, TAG_COUPLING << 24)) is below 128
+    dims, L, seed = 3, 4, (1 << 35) | 13
+    J = oracle.couplings(dims, L, seed, realisation)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for b in range(J.size):
+        blk = oracle.philox([b >> 4, realisation, 0, oracle.TAG_COUPLING << 24], key)
+        assert J[b] == (1 if _gather_byte(blk, b & 15) < 128 else -1), b
+
+
+def test_couplings_of_different_realisations_are_independent_fair_coins():
+    # 64 realisations of a 16^3 lattice: +1 with p = 1/2, and two realisations
+    # agree on a bond with p = 1/2 (binomial 5 sigma bounds)
+    Js = np.stack([oracle.couplings(3, 16, 13, k) for k in range(64)]).astype(np.float64)
+    n = Js.size
+    assert abs((Js > 0).mean() - 0.5) < 5 * 0.5 / np.sqrt(n)
+    agree = (Js[1:] == Js[:-1]).mean()
+    assert abs(agree - 0.5) < 5 * 0.5 / np.sqrt(Js[1:].size)
+    assert np.array_equal(Js[0], oracle.couplings(3, 16, 13).astype(np.float64))

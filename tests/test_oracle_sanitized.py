@@ -29,6 +29,8 @@ void orc_metropolis_table(double, int, uint64_t *);
 void orc_heatbath_table(double, int, uint64_t *);
 int orc_init(int, int, int, int, int8_t *, int, uint64_t, uint32_t);
 int orc_couplings(int, int, int, int, int8_t *, uint64_t);
+int orc_couplings_of(int, int, int, int, int8_t *, uint64_t, uint32_t);
+int orc_sweep_dcb(int, int, int, int8_t *, double, uint64_t, uint32_t, uint64_t, int, int64_t *);
 void orc_measure(int, int, int, int, const int8_t *, const int8_t *, int64_t *, int64_t *);
 int orc_sweep(int, int, int, int, int8_t *, const int8_t *, int, double, uint64_t, uint32_t, uint64_t, int,
               int64_t *);
@@ -52,6 +54,7 @@ static int lattice_case(int dims, int Lx, int Ly, int Lz, int rule, int withJ)
     int64_t *EM = malloc(sizeof(int64_t) * 2 * 12), E, M;
     CHECK(orc_init(dims, Lx, Ly, Lz, s, 1, 7, 3) == 0);
     if (J) CHECK(orc_couplings(dims, Lx, Ly, Lz, J, 11) == 0);
+    if (J) CHECK(orc_couplings_of(dims, Lx, Ly, Lz, J, 11, 5) == 0);
     memcpy(t, s, (size_t)N);
     CHECK(orc_sweep(dims, Lx, Ly, Lz, s, J, rule, 0.4, 5, 3, 0, 12, EM) == 0);
     CHECK(orc_sweep(dims, Lx, Ly, Lz, t, J, rule, 0.4, 5, 3, 0, 5, NULL) == 0);
@@ -86,6 +89,13 @@ int main(void)
         CHECK(orc_init(2, 3, 3, 1, s, 1, 3, 0) == 0);
         CHECK(orc_sweep_q3(3, s, 0.3, 3, 0, 0, 4, EM) == 0);
         CHECK(orc_sweep(2, 5, 4, 1, s, NULL, 0, 0.3, 1, 0, 0, 1, NULL) == -1);  /* odd extent rejected */
+    }
+    {
+        int8_t s[144];
+        int64_t EM[6];
+        CHECK(orc_init(2, 12, 12, 1, s, 1, 3, 0) == 0);
+        CHECK(orc_sweep_dcb(12, 2, 3, s, 0.4, 3, 0, 5, 3, EM) == 0);
+        CHECK(orc_sweep_dcb(12, 4, 1, s, 0.4, 3, 0, 5, 3, EM) == -1);  /* 3 tiles per side: not a checkerboard */
     }
     {
         const int64_t R = 64 * 64 + 64 * 3 + 7;
