@@ -19,11 +19,14 @@
 // joins a tile of colour 0 to one of colour 1.  Colour-0 tiles are final
 // after their launch and add their internal bonds and spins; colour-1 tiles
 // add theirs plus all bonds across their edges (the other ends are final).
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace mcs {
 
 constexpr int kDcbTieQueue = 512;
+constexpr int kDcbMaxWaves = 4;  // at most 256 threads per workgroup
 
 struct DcbArgs {
     uint32_t *lat;              // packed lattices, rows of 2 L/64 words (even-x array first)
@@ -50,8 +53,8 @@ __global__ __launch_bounds__(256) void k_dcb(DcbArgs a)
 {
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t q_ws[kDcbTieQueue], q_blk[kDcbTieQueue], q_p8[kDcbTieQueue], q_p4[kDcbTieQueue];
-    __shared__ uint32_t q_cnt[4];
-    __shared__ long long red[2][4];
+    __shared__ uint32_t q_cnt[kDcbMaxWaves];
+    __shared__ long long red[2][kDcbMaxWaves];
     const int l = blockIdx.y;
     int tx, ty;
     dcb_tile(a, blockIdx.x, tx, ty);
@@ -82,12 +85,25 @@ __global__ __launch_bounds__(256) void k_dcb(DcbArgs a)
     const TopMask m4 = top_mask(a.t4.top), m8 = top_mask(a.t8.top);
     const uint32_t wq_cap = (uint32_t)(kDcbTieQueue / nwaves), wq_base = (uint32_t)wave * wq_cap;
 
-    // ---- load the tile and its halo (corner words are not needed)
+    // ---- load the tile and its halo (corner words are not needed), a batch
+    // of words per thread in flight at once
     const int ld = rows * 2 * Ww;
-    for (int i = tid; i < ld; i += nt) {
-        const int r = i / (2 * Ww), rem = i - r * 2 * Ww, par = rem / Ww, c = rem - par * Ww;
-        const bool corner = (r == 0 || r == rows - 1) && (c == 0 || c == Ww - 1);
-        lds[i] = corner ? 0u : lat[((size_t)gy(r) * 2 + par) * Wl + gw(c)];
+    constexpr int kLoadBatch = 8;
+    for (int i0 = tid; i0 < ld; i0 += kLoadBatch * nt) {
+        uint32_t v[kLoadBatch];
+#pragma unroll
+        for (int j = 0; j < kLoadBatch; ++j) {
+            const int i = i0 + j * nt;
+            v[j] = 0u;
+            if (i < ld) {
+                const int r = i / (2 * Ww), rem = i - r * 2 * Ww, par = rem / Ww, c = rem - par * Ww;
+                const bool corner = (r == 0 || r == rows - 1) && (c == 0 || c == Ww - 1);
+                if (!corner) v[j] = lat[((size_t)gy(r) * 2 + par) * Wl + gw(c)];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kLoadBatch; ++j)
+            if (i0 + j * nt < ld) lds[i0 + j * nt] = v[j];
     }
     __syncthreads();
 
@@ -267,7 +283,9 @@ hipError_t launch_dcb_phase(uint32_t *packed, int L, int T, int count, int coars
     a.t8 = tab.met[2];
     a.EM = EM;
     const int tiles = (L / T) * (L / T) / 2;
-    hipLaunchKernelGGL(k_dcb, dim3((unsigned)tiles, (unsigned)count), dim3(256), dcb_lds_bytes(T), s, a);
+    // one thread per word of a colour (T^2 / 64 of them), at most 256
+    const int threads = std::min(256, T * T / 64);
+    hipLaunchKernelGGL(k_dcb, dim3((unsigned)tiles, (unsigned)count), dim3(threads), dcb_lds_bytes(T), s, a);
     return hipGetLastError();
 }
 

@@ -193,11 +193,24 @@ __device__ void place_copies(const PaPop &P)
         const int i0 = base + tid * kPlacePer;
         int c[kPlacePer];
         int s = 0;
+        // the counts were added by other workgroups' atomics and are read after
+        // the caller's device-scope fence; a full chunk is 16-byte aligned
+        if (i0 + kPlacePer <= R) {
+            const int4 *v = (const int4 *)(P.n + i0);
 #pragma unroll
-        for (int k = 0; k < kPlacePer; ++k) {
-            c[k] = i0 + k < R ? __hip_atomic_load(&P.n[i0 + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
-            s += c[k];
+            for (int k = 0; k < kPlacePer / 4; ++k) {
+                const int4 q = v[k];
+                c[4 * k] = q.x;
+                c[4 * k + 1] = q.y;
+                c[4 * k + 2] = q.z;
+                c[4 * k + 3] = q.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kPlacePer; ++k) c[k] = i0 + k < R ? P.n[i0 + k] : 0;
         }
+#pragma unroll
+        for (int k = 0; k < kPlacePer; ++k) s += c[k];
         const int incl = wave_scan_i32(s, lane);
         if (lane == 63) wsum[wave] = incl;
         __syncthreads();
