@@ -199,6 +199,30 @@ size_t mc_dcb_workspace_bytes(const mc_geom *geom);
 int mc_sweep_dcb(mc_ctx *ctx, const mc_geom *geom, void *spins, const mc_sweep_args *args, int32_t tile, int32_t hits,
                  int64_t *EM, void *ws, size_t ws_bytes, void *stream);
 
+/* Spin glasses multi-spin coded across disorder realisations (Sec.
+ * "Disordered systems": the bits of a word are 64 realisations, each with its
+ * own couplings; the coded copies share one random number per site).
+ * mc_couplings_msc64: bimodal couplings of realisation k = realisation0 +
+ *   64 l + b in bit b of word (l, d, i) of J (device uint64 [count][dims][N],
+ *   bond (i, i + e_d), bit set <=> J = -1): exactly the couplings
+ *   mc_couplings gives, but with counter word 1 = k (realisation 0 is
+ *   mc_couplings' own).  geom: layout MC_MSC64.  Stream-ordered.
+ * mc_sweep_sg_msc64: nsweeps checkerboard sweeps (rules as mc_sweep) of
+ *   every realisation of the word lattices spins (MC_MSC64, bit b of word
+ *   lattice l = realisation 64 l + b, e.g. initialised by mc_init: lane b is
+ *   then the hot start of replica replica0 + 64 l + b) with couplings J (as
+ *   above).  All 64 realisations of word lattice l draw the random numbers of
+ *   replica id args->replica0 + l (the draw of mc_sweep for that replica and
+ *   site): lane b evolves exactly as the int8 lattice of realisation 64 l + b
+ *   under mc_sweep with replica id replica0 + l.  EM: device int64
+ *   [nsweeps][count * 64][2] or NULL.  MC_E_LAYOUT unless MC_MSC64;
+ *   MC_E_SHAPE unless the sites of one colour are a multiple of 64.
+ *   Stream-ordered.                                                         */
+int mc_couplings_msc64(mc_ctx *ctx, const mc_geom *geom, uint64_t *J, uint64_t seed, uint32_t realisation0,
+                       void *stream);
+int mc_sweep_sg_msc64(mc_ctx *ctx, const mc_geom *geom, uint64_t *spins, const uint64_t *J, const mc_sweep_args *args,
+                      int64_t *EM, void *stream);
+
 /* E and M of every lattice (lane) as in mc_sweep; EM: device int64
  * [count * lanes][2].  Stream-ordered.                                      */
 int mc_measure(mc_ctx *ctx, const mc_geom *geom, const void *spins, const int8_t *J, int64_t *EM,

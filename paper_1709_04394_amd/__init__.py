@@ -113,6 +113,10 @@ _lib_fns = dict(
     mc_static_scratch_bytes=_sig("mc_static_scratch_bytes", _c.c_size_t, []),
     mc_sweep_noalloc=_sig("mc_sweep_noalloc", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _c.POINTER(SweepArgs), _vp,
                                                          _vp]),
+    mc_couplings_msc64=_sig("mc_couplings_msc64", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _c.c_uint64, _c.c_uint32,
+                                                             _vp]),
+    mc_sweep_sg_msc64=_sig("mc_sweep_sg_msc64", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _vp, _c.POINTER(SweepArgs),
+                                                           _vp, _vp]),
     mc_dcb_workspace_bytes=_sig("mc_dcb_workspace_bytes", _c.c_size_t, [_c.POINTER(Geom)]),
     mc_sweep_dcb=_sig("mc_sweep_dcb", _c.c_int, [_vp, _c.POINTER(Geom), _vp, _c.POINTER(SweepArgs), _c.c_int32,
                                                  _c.c_int32, _vp, _vp, _c.c_size_t, _vp]),
@@ -269,6 +273,19 @@ class Context:
         a = SweepArgs(rule, float(beta), seed, replica0, sweep0, nsweeps)
         return self._check(_lib.mc_sweep_noalloc(self._h, ctypes.byref(geom), _ptr(spins), _ptr(J), ctypes.byref(a),
                                                  _ptr(EM), _stream(self.device)), "mc_sweep_noalloc")
+
+    def couplings_msc64(self, geom, J, seed, realisation0=0):
+        """Couplings of 64 realisations per word (mc_couplings_msc64) into J,
+        an int64 tensor [count, dims * N] (bit-identical to uint64)."""
+        return self._check(_lib.mc_couplings_msc64(self._h, ctypes.byref(geom), _ptr(J), seed, realisation0,
+                                                   _stream(self.device)), "mc_couplings_msc64")
+
+    def sweep_sg_msc64(self, geom, spins, J, beta, seed, nsweeps, sweep0=0, replica0=0, rule=METROPOLIS, EM=None):
+        """Sweeps of spin glasses coded across realisations, one shared random
+        number per site (mc_sweep_sg_msc64)."""
+        a = SweepArgs(rule, float(beta), seed, replica0, sweep0, nsweeps)
+        return self._check(_lib.mc_sweep_sg_msc64(self._h, ctypes.byref(geom), _ptr(spins), _ptr(J), ctypes.byref(a),
+                                                  _ptr(EM), _stream(self.device)), "mc_sweep_sg_msc64")
 
     def dcb_workspace_bytes(self, geom):
         return int(_lib.mc_dcb_workspace_bytes(ctypes.byref(geom)))

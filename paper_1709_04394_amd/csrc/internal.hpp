@@ -153,6 +153,14 @@ hipError_t launch_dcb_phase(uint32_t *packed, int L, int T, int count, int coars
                             uint64_t sweep, uint32_t seed_lo, uint32_t seed_hi, const SweepTables &tab, int64_t *EM,
                             hipStream_t s);
 
+// +-J spin glasses multi-spin coded across 64 disorder realisations with one
+// random number per site shared by the coded copies (k_sg_msc.hip)
+bool sg_msc_supported(const Geom &g);
+hipError_t launch_couplings_msc64(const Geom &g, uint64_t *J, uint64_t seed, uint32_t realisation0, hipStream_t s);
+hipError_t launch_sg_msc_phase(const Geom &g, int rule, const SweepTables &tab, uint64_t *words, const uint64_t *J,
+                               uint32_t seed_lo, uint32_t seed_hi, uint32_t replica0, uint64_t sweep, int phase,
+                               int64_t *EM, hipStream_t s);
+
 // Sweep driver: chooses the fused kernel when the geometry and the workspace
 // allow it, the generic two-launch half-sweeps otherwise.
 size_t fused_workspace_bytes(const Geom &g, int layout);

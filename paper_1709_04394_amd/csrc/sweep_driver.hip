@@ -462,3 +462,52 @@ int mc_sweep_dcb(mc_ctx *ctx, const mc_geom *geom, void *spins, const mc_sweep_a
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Spin glasses multi-spin coded across disorder realisations (64 per word),
+// one random number per site shared by the coded realisations.
+extern "C" {
+
+int mc_couplings_msc64(mc_ctx *ctx, const mc_geom *geom, uint64_t *J, uint64_t seed, uint32_t realisation0,
+                       void *stream)
+{
+    if (!ctx) return MC_E_INVAL;
+    int rc = check_geom(ctx, geom, true);
+    if (rc) return rc;
+    if (geom->layout != MC_MSC64) return fail(ctx, MC_E_LAYOUT, "coupling words need MC_MSC64");
+    if (!J) return fail(ctx, MC_E_INVAL, "J is NULL");
+    if ((uint64_t)realisation0 + 64ull * (uint64_t)geom->count > 4294967296ull)
+        return fail(ctx, MC_E_RANGE, "realisation ids exceed 32 bits");
+    const Geom g = to_geom(geom);
+    if ((double)g.dims * (double)g.N > 4294967296.0 * 16) return fail(ctx, MC_E_SHAPE, "too many bonds");
+    if ((rc = set_device(ctx))) return rc;
+    return device_check(ctx, launch_couplings_msc64(g, J, seed, realisation0, (hipStream_t)stream),
+                        "mc_couplings_msc64 launch");
+}
+
+int mc_sweep_sg_msc64(mc_ctx *ctx, const mc_geom *geom, uint64_t *spins, const uint64_t *J, const mc_sweep_args *args,
+                      int64_t *EM, void *stream)
+{
+    if (!ctx) return MC_E_INVAL;
+    int rc = check_sweep_args(ctx, geom, spins, args);
+    if (rc) return rc;
+    if (geom->layout != MC_MSC64) return fail(ctx, MC_E_LAYOUT, "realisation coding needs MC_MSC64");
+    if (!J) return fail(ctx, MC_E_INVAL, "J is NULL");
+    const Geom g = to_geom(geom);
+    if (!sg_msc_supported(g))
+        return fail(ctx, MC_E_SHAPE, "the sites of one colour must be a multiple of 64 (N = %lld)", (long long)g.N);
+    if (args->nsweeps == 0) return MC_OK;
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const SweepTables tab = build_tables(args->beta);
+    const int64_t em_stride = 2 * 64 * (int64_t)g.count;
+    hipError_t e = EM ? launch_fill_i64(EM, (int64_t)args->nsweeps * em_stride, 0, s) : hipSuccess;
+    for (int t = 0; t < args->nsweeps && e == hipSuccess; ++t)
+        for (int phase = 0; phase < 2 && e == hipSuccess; ++phase)
+            e = launch_sg_msc_phase(g, args->rule, tab, spins, J, (uint32_t)args->seed, (uint32_t)(args->seed >> 32),
+                                    args->replica0, args->sweep0 + (uint64_t)t, phase,
+                                    EM ? EM + t * em_stride : nullptr, s);
+    return device_check(ctx, e, "mc_sweep_sg_msc64");
+}
+
+}  // extern "C"

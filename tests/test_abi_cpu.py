@@ -302,3 +302,25 @@ def test_dcb_argument_checks():
         assert call(g, nsw=0) == 0  # nothing to do: no device work
     finally:
         mcs._lib.mc_ctx_destroy(h)
+
+
+def test_sg_msc64_argument_checks():
+    """mc_couplings_msc64 and mc_sweep_sg_msc64 validate before any device
+    work (no GPU needed)."""
+    h = ctypes.c_void_p()
+    assert mcs._lib.mc_ctx_create(ctypes.byref(h), 0) == 0
+    try:
+        fake = ctypes.c_void_p(1)
+        g = mcs.make_geom(3, 32, layout=mcs.MSC64)
+        a = mcs.SweepArgs(0, 1.0, 1, 0, 0, 2)
+        assert mcs._lib.mc_sweep_sg_msc64(h, ctypes.byref(mcs.make_geom(3, 32)), fake, fake, ctypes.byref(a), None,
+                                          None) == mcs.MC_E_LAYOUT
+        assert mcs._lib.mc_sweep_sg_msc64(h, ctypes.byref(g), fake, None, ctypes.byref(a), None, None) == mcs.MC_E_INVAL
+        small = mcs.make_geom(2, (8, 4), layout=mcs.MSC64)  # 16 sites of a colour: not a multiple of 64
+        assert mcs._lib.mc_sweep_sg_msc64(h, ctypes.byref(small), fake, fake, ctypes.byref(a), None,
+                                          None) == mcs.MC_E_SHAPE
+        assert mcs._lib.mc_couplings_msc64(h, ctypes.byref(mcs.make_geom(3, 32)), fake, 1, 0, None) == mcs.MC_E_LAYOUT
+        assert mcs._lib.mc_couplings_msc64(h, ctypes.byref(g), None, 1, 0, None) == mcs.MC_E_INVAL
+        assert mcs._lib.mc_couplings_msc64(h, ctypes.byref(g), fake, 1, 0xFFFFFFC1, None) == mcs.MC_E_RANGE
+    finally:
+        mcs._lib.mc_ctx_destroy(h)
