@@ -201,7 +201,8 @@ def main(argv=None):
       converge --L L --seeds S,.. --out DIR
             training sizes and the MLP (once), then both arms to a flat
             histogram for every seed: DIR/lnW_<arm>_<S>.npy, DIR/lnW_init.npy,
-            DIR/converge.json
+            DIR/mlp_params.npy, DIR/converge.json; run again on the same DIR,
+            it reuses the network and skips the seeds already run
       produce --dir DIR --arm A --seed S --pseed P --walkers W --burn B
               --checkpoints C1,..,Cn
             production at the arm's converged weights of seed S (walker seed
@@ -269,10 +270,23 @@ def main(argv=None):
     if a.stage == "converge":
         os.makedirs(a.out, exist_ok=True)
         seeds = [int(x) for x in a.seeds.split(",")]
-        lnW_by_L, _ = training_weights(ctx)
-        params, log = train_network(ctx, lnW_by_L)
-        conv = {"L": a.L, "seeds": seeds, "mlp_loss": [float(log[0]), float(log[-1])], "runs": {}}
+        pfile, cfile = os.path.join(a.out, "mlp_params.npy"), os.path.join(a.out, "converge.json")
+        if os.path.exists(pfile) and os.path.exists(cfile):
+            # resume: the trained network and the seeds already run are kept
+            # (training is seeded, so retraining would give the same network)
+            params = torch.from_numpy(np.load(pfile)).to(ctx.device)
+            conv = json.load(open(cfile))
+            if int(conv["L"]) != a.L:
+                raise SystemExit("%s holds L=%d, not L=%d" % (cfile, conv["L"], a.L))
+            conv["seeds"] = list(dict.fromkeys([int(x) for x in conv["seeds"]] + seeds))
+        else:
+            lnW_by_L, _ = training_weights(ctx)
+            params, log = train_network(ctx, lnW_by_L)
+            np.save(pfile, params.cpu().numpy())
+            conv = {"L": a.L, "seeds": seeds, "mlp_loss": [float(log[0]), float(log[-1])], "runs": {}}
         for sd in seeds:
+            if str(sd) in conv["runs"]:
+                continue
             r = compare(ctx, a.L, params, seed=sd, prod_sweeps=0)
             conv["runs"][str(sd)] = {arm: arm_summary(r[arm]) for arm in ("plain", "learned")}
             conv["runs"][str(sd)]["learned"]["fallback"] = bool(r["learned"]["fallback"])
