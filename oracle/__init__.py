@@ -28,6 +28,7 @@ _LIB = os.path.join(_HERE, "libmcoracle.so")
 TAG_INIT, TAG_SWEEP, TAG_COUPLING, TAG_RESAMPLE = 1, 2, 3, 4
 TAG_MUCA, TAG_MLP_INIT, TAG_SWEEP_LO, TAG_MUCA_LO = 5, 6, 7, 8
 TAG_EXCHANGE = 9
+TAG_WINDOW = 10
 METROPOLIS, HEATBATH = 0, 1
 COLD, HOT = 0, 1
 
@@ -89,6 +90,12 @@ def lib():
         L.orc_muca_settle.argtypes = [ctypes.c_int, ctypes.c_int, u8p, u8p]
         L.orc_muca_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, u8p, u8p, u8p, ctypes.c_uint64,
                                       ctypes.c_uint64, ctypes.c_int, ctypes.c_int, u8p]
+        L.orc_wl_threshold.argtypes = [ctypes.c_uint64]
+        L.orc_wl_threshold.restype = ctypes.c_uint64
+        L.orc_win_drive.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u8p, u8p, ctypes.c_uint64,
+                                    ctypes.c_int, u8p, u8p]
+        L.orc_wl_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u8p, u8p, ctypes.c_int, u8p, u8p,
+                                    ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, u8p, u8p, u8p, u8p]
         _lib = L
     return _lib
 
@@ -461,3 +468,146 @@ def pt_run(dims, L, beta, seed, rounds, theta, rule=METROPOLIS, start=HOT, pt_se
         E_at[rnd] = [E[replica_at[i]] for i in range(nT)]
         pt_exchange(beta, E, temp_of, replica_at, seed, rnd, accepted, pt_set)
     return dict(E_at=E_at, temp_of=temp_of, replica_at=replica_at, accepted=accepted, spins=spins)
+
+
+# ------------------------------------------------------ Wang-Landau in windows
+# Sec. "Wang-Landau update": g(E) starts at 1 and is multiplied by f at every
+# visit, moves are accepted with min[1, g(E)/g(E')], f -> sqrt(f) once the
+# histogram is flat (minimum >= 80 % of the mean), until ln f is below a
+# threshold.  Parallel form (same section, and the windows of Sec.
+# "Multicanonical simulations"): the level range is split into overlapping
+# windows, each sampled by M walkers with their own estimates; a move out of
+# the window is rejected and the current level counted again; the walkers'
+# estimates are averaged when all of a window's walkers have flat histograms,
+# before f is reduced; the windows' pieces are matched on their overlaps.
+WL_ONE = 1 << 32  # ln g unit: estimates are integers in units of 2^-32
+
+
+def wl_threshold(x):
+    """ceil(exp(-x 2^-32) 2^32), at least 1, for an estimate difference x > 0
+    (the table product of orc_wl_threshold)."""
+    return int(lib().orc_wl_threshold(int(x)))
+
+
+def _windows(lo, hi):
+    lo = np.ascontiguousarray(lo, dtype=np.int32)
+    hi = np.ascontiguousarray(hi, dtype=np.int32)
+    return lo, hi, int((hi - lo).max()) + 1
+
+
+def win_drive(L, lo, hi, M, seed, max_pass=1000):
+    """Walkers of every window driven from the ground state into their window
+    (orc_win_drive); returns (spins [nwin M][N], E [nwin M])."""
+    lo, hi, _ = _windows(lo, hi)
+    W = lo.size * M
+    spins = np.zeros((W, L * L), dtype=np.int8)
+    E = np.zeros(W, dtype=np.int64)
+    _check(lib().orc_win_drive(L, lo.size, M, _p(lo), _p(hi), seed, max_pass, _p(spins), _p(E)), "win_drive")
+    return spins, E
+
+
+def wl_sweeps(L, lo, hi, M, inc, active, seed, sweep0, nsweeps, spins, E, G, H):
+    """nsweeps Wang-Landau sweeps of the walkers of the active windows
+    (orc_wl_sweeps), in place on spins, E, G [nwin M][wmax], H [nwin M][wmax]."""
+    lo, hi, wmax = _windows(lo, hi)
+    assert G.shape == (lo.size * M, wmax) and H.shape == G.shape
+    inc = np.ascontiguousarray(inc, dtype=np.int64)
+    act = np.ascontiguousarray(active, dtype=np.uint8)
+    _check(lib().orc_wl_sweeps(L, lo.size, M, _p(lo), _p(hi), wmax, _p(inc), _p(act), seed, sweep0, nsweeps,
+                               _p(spins), _p(E), _p(G), _p(H)), "wl_sweeps")
+
+
+def wl_levels_with_states(lo, hi):
+    """Window levels that have states on the 2D L x L torus (L >= 4): all of
+    [lo, hi] but level 1 (E = -2N + 4)."""
+    return [k for k in range(lo, hi + 1) if k != 1]
+
+
+def wl_flat(Hw, lo, hi, flat):
+    """min H >= flat * mean H over the window levels with states."""
+    ks = [k - lo for k in wl_levels_with_states(lo, hi)]
+    h = [int(Hw[j]) for j in ks]
+    return float(min(h)) * float(len(h)) >= flat * float(sum(h))
+
+
+def wl_average(G, lo, hi, M, i):
+    """Average of window i's walker estimates (floor of the integer mean per
+    level), shifted so that its minimum over the levels with states is 0, then
+    given to every walker of the window."""
+    n = hi[i] - lo[i] + 1
+    rows = G[i * M:(i + 1) * M, :n]
+    avg = np.array([sum(int(v) for v in rows[:, j]) // M for j in range(n)], dtype=np.int64)
+    ks = [k - lo[i] for k in wl_levels_with_states(lo[i], hi[i])]
+    avg -= min(int(avg[j]) for j in ks)
+    G[i * M:(i + 1) * M, :n] = avg
+    return avg
+
+
+def wl_match(lo, hi, pieces, K):
+    """One ln g over [0, K] from the windows' pieces (pieces[i][k - lo_i]):
+    window i + 1 is shifted by the mean of (previous, shifted) - (own) over the
+    overlap levels with states; level k takes window i's value up to the middle
+    of each overlap, mid = (lo_{i+1} + hi_i) div 2; then ln g(0) = ln 2 (the two
+    ground states) and ln g(1) = -inf (no states)."""
+    out = np.full(K + 1, np.nan)
+    prev = np.asarray(pieces[0], dtype=np.float64)
+    out[lo[0]:hi[0] + 1] = prev
+    for i in range(1, len(lo)):
+        cur = np.asarray(pieces[i], dtype=np.float64)
+        ov = [k for k in wl_levels_with_states(lo[i], hi[i - 1])]
+        if not ov:
+            raise ValueError("windows %d and %d share no level with states" % (i - 1, i))
+        s = 0.0
+        for k in ov:
+            s = s + (prev[k - lo[i - 1]] - cur[k - lo[i]])
+        cur = cur + s / len(ov)
+        mid = (lo[i] + hi[i - 1]) // 2
+        out[mid + 1:hi[i] + 1] = cur[mid + 1 - lo[i]:]
+        prev = cur
+    out = out - out[0] + math.log(2.0)
+    if K >= 1:
+        out[1] = -np.inf
+    return out
+
+
+def wl_run(L, lo, hi, M, seed, lnf_final, flat=0.8, check=1, max_sweeps=1 << 30, max_pass=1000):
+    """Wang-Landau sampling in windows: walkers driven into their windows;
+    stage s of window i has ln f = 2^-s (f = e at s = 0); after every `check`
+    sweeps of the active windows, a window whose walkers all have flat
+    histograms averages their estimates (wl_average), clears the histograms
+    and halves ln f, and stops once ln f < lnf_final.  Returns the windows'
+    final pieces (averaged estimates in units of 1), the matched ln g, and per
+    window the stages completed and the sweeps run."""
+    lo, hi, wmax = _windows(lo, hi)
+    nwin = lo.size
+    N = L * L
+    K = N // 2
+    spins, E = win_drive(L, lo, hi, M, seed, max_pass)
+    G = np.zeros((nwin * M, wmax), dtype=np.int64)
+    H = np.zeros((nwin * M, wmax), dtype=np.uint32)
+    stage = [0] * nwin
+    active = [1] * nwin
+    sweeps = [0] * nwin
+    sweep = 0
+    while any(active) and sweep < max_sweeps:
+        inc = [WL_ONE >> stage[i] for i in range(nwin)]
+        wl_sweeps(L, lo, hi, M, inc, active, seed, sweep, check, spins, E, G, H)
+        sweep += check
+        for i in range(nwin):
+            if not active[i]:
+                continue
+            sweeps[i] += check
+            if all(wl_flat(H[w], lo[i], hi[i], flat) for w in range(i * M, (i + 1) * M)):
+                wl_average(G, lo, hi, M, i)
+                H[i * M:(i + 1) * M] = 0
+                stage[i] += 1
+                if math.ldexp(1.0, -stage[i]) < lnf_final:
+                    active[i] = 0
+    pieces = []
+    for i in range(nwin):
+        if active[i]:
+            wl_average(G, lo, hi, M, i)  # unfinished window: its current average
+        n = hi[i] - lo[i] + 1
+        pieces.append(G[i * M, :n].astype(np.float64) / float(WL_ONE))
+    return dict(pieces=pieces, lng=wl_match(lo, hi, pieces, K), stages=stage, sweeps=sweeps,
+                converged=[not a for a in active], spins=spins, E=E, G=G, H=H, sweep=sweep)

@@ -25,6 +25,10 @@
  *   population annealing ..... Sec. "Population annealing", Eq. (Q)
  *   multicanonical sweeps .... Sec. "Multicanonical simulations", Eq. (muca),
  *                              sequential site order, count-again rule
+ *   Wang-Landau in windows ... Sec. "Wang-Landau update" (g(E) <- f g(E) per
+ *                              visit, acceptance min[1, g(E)/g(E')]); energy
+ *                              windows with the count-again rule of Sec.
+ *                              "Multicanonical simulations"
  *
  * Floating point: plain IEEE double, -O2 -ffp-contract=off, no fast-math.
  * Every exp/log that decides a trajectory goes through the C library's exp()
@@ -86,7 +90,8 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
  * variate of the paper is r / 2^32 in [0,1).                                  */
 enum {
     ORC_TAG_INIT = 1, ORC_TAG_SWEEP = 2, ORC_TAG_COUPLING = 3, ORC_TAG_RESAMPLE = 4,
-    ORC_TAG_MUCA = 5, ORC_TAG_MLP_INIT = 6, ORC_TAG_SWEEP_LO = 7, ORC_TAG_MUCA_LO = 8
+    ORC_TAG_MUCA = 5, ORC_TAG_MLP_INIT = 6, ORC_TAG_SWEEP_LO = 7, ORC_TAG_MUCA_LO = 8,
+    ORC_TAG_WINDOW = 10
 };
 
 static void orc_block(uint64_t seed, uint32_t tag, uint32_t a, uint32_t replica,
@@ -671,5 +676,156 @@ int orc_muca_sweeps(int L, int walkers, int8_t *spins, int64_t *E, const double 
             for (int64_t k = 0; k <= K; ++k) H[k] += Hw[w * (K + 1) + k];
     free(Hw);
     free(T);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Wang-Landau sampling in energy windows (Sec. "Wang-Landau update").  Energy
+ * levels k = (E + 2N)/4 of the 2D L x L torus; window i holds the levels
+ * [lo_i, hi_i] within [0, N/2] (E <= 0) and is sampled by M walkers, walker w
+ * (of nwin M) in window w / M.  Each walker keeps its own estimate of ln g
+ * over its window's levels, G_w[k - lo] in units of 2^-32 (int64), and its own
+ * visit counts H_w[k - lo]; both arrays have wmax entries per walker.
+ *
+ * One update of a walker: the typewriter site order of the multicanonical
+ * walkers; the level k2 after a flip; a move out of the window is rejected
+ * and the current level counted again; otherwise the move is accepted with
+ * min[1, g(E)/g(E')] = exp(-(G[k2] - G[k]) 2^-32) when G[k2] > G[k] (always
+ * when G[k2] <= G[k]), by r32 < ceil(p 2^32) with r32 word (i mod 4) of
+ * Philox(MUCA, i div 4, w, sweep).  After the update, G[k] += inc (ln f in
+ * units of 2^-32) and H[k] += 1 at the level the walker is at.
+ *
+ * The exponential of an estimate difference x (units of 2^-32) is the product,
+ * in this order, of exp(-n), exp(-a 2^-8), exp(-b 2^-16), exp(-c 2^-24) and
+ * exp(-d 2^-32), x = n 2^32 + a 2^24 + b 2^16 + c 2^8 + d, each factor from
+ * libm exp in FP64; n >= 23 gives p < 2^-32, i.e. the threshold 1.          */
+#define ORC_WL_NEXP 23
+
+static void orc_wl_exp_tables(double *en, double *t8, double *t16, double *t24, double *t32)
+{
+    for (int n = 0; n < ORC_WL_NEXP; ++n) en[n] = exp(-(double)n);
+    for (int a = 0; a < 256; ++a) {
+        t8[a] = exp(-(double)a / 256.0);
+        t16[a] = exp(-(double)a / 65536.0);
+        t24[a] = exp(-(double)a / 16777216.0);
+        t32[a] = exp(-(double)a / 4294967296.0);
+    }
+}
+
+/* ceil(exp(-x 2^-32) 2^32) for x > 0 (at least 1) */
+uint64_t orc_wl_threshold(uint64_t x)
+{
+    static double en[ORC_WL_NEXP], t8[256], t16[256], t24[256], t32[256];
+    static int ready = 0;
+    if (!ready) {
+        #pragma omp critical(orc_wl_tab)
+        {
+            if (!ready) { orc_wl_exp_tables(en, t8, t16, t24, t32); ready = 1; }
+        }
+    }
+    uint64_t n = x >> 32;
+    if (n >= ORC_WL_NEXP) return 1;
+    uint32_t lo = (uint32_t)x;
+    double p = en[n];
+    p = p * t8[lo >> 24];
+    p = p * t16[(lo >> 16) & 255u];
+    p = p * t24[(lo >> 8) & 255u];
+    p = p * t32[lo & 255u];
+    uint64_t T = (uint64_t)ceil(ldexp(p, 32));
+    return T < 1 ? 1 : T;
+}
+
+/* Walkers into their windows: every walker starts from the ground state (all
+ * +1, level 0) and runs typewriter passes in which a flip is taken iff the
+ * walker is still below its window, the flip raises its level, and the top
+ * bit of word (i mod 4) of Philox(WINDOW, i div 4, w, pass) is set; it stops
+ * at the first level >= lo.  A flip moves the level by at most 2 and a window
+ * spans at least 2 levels, so the walker stops inside.  Below E = 0 some flip
+ * always raises the energy, so the walk cannot stall.  Returns -1 unless
+ * every window is within [0, N/2] with hi - lo >= 1 and every walker arrived
+ * within max_pass passes.                                                    */
+int orc_win_drive(int L, int nwin, int M, const int32_t *lo, const int32_t *hi, uint64_t seed, int max_pass,
+                  int8_t *spins, int64_t *E)
+{
+    if (L < 4 || (L & 1) || nwin < 1 || M < 1) return -1;
+    int64_t N = (int64_t)L * L, K = N / 2;
+    for (int i = 0; i < nwin; ++i)
+        if (lo[i] < 0 || hi[i] > K || hi[i] - lo[i] < 1) return -1;
+    orc_geom g = mkgeom(2, L, L, 1);
+    int bad = 0;
+    #pragma omp parallel for schedule(dynamic) reduction(|:bad)
+    for (int64_t w = 0; w < (int64_t)nwin * M; ++w) {
+        int8_t *s = spins + w * N;
+        int64_t klo = lo[w / M], k = 0;
+        for (int64_t i = 0; i < N; ++i) s[i] = 1;
+        for (int pass = 0; pass < max_pass && k < klo; ++pass)
+            for (int y = 0; y < L && k < klo; ++y)
+                for (int x = 0; x < L && k < klo; ++x) {
+                    int64_t i = site(&g, x, y, 0);
+                    int dl = 2 * s[i] * local_field(&g, s, NULL, x, y, 0) / 4;
+                    if (dl <= 0) continue;
+                    uint32_t r = orc_draw_word(seed, ORC_TAG_WINDOW, (uint32_t)i, (uint32_t)w, (uint64_t)pass);
+                    if (r >> 31) { s[i] = (int8_t)-s[i]; k += dl; }
+                }
+        if (k < klo) bad = 1;
+        E[w] = 4 * k - 2 * N;
+    }
+    return bad ? -1 : 0;
+}
+
+/* nsweeps Wang-Landau sweeps (above) of the walkers of every window i with
+ * active[i] (others are left as they are); inc[i] is ln f of window i in
+ * units of 2^-32 (0: fixed weights, i.e. multicanonical sweeps with ln W =
+ * -G 2^-32 in the window).  Afterwards each swept walker's estimate is shifted
+ * to a minimum of 0 over its window's levels with states.                   */
+int orc_wl_sweeps(int L, int nwin, int M, const int32_t *lo, const int32_t *hi, int wmax, const int64_t *inc,
+                  const uint8_t *active, uint64_t seed, uint64_t sweep0, int nsweeps, int8_t *spins, int64_t *E,
+                  int64_t *G, uint32_t *H)
+{
+    if (L < 4 || (L & 1) || nwin < 1 || M < 1 || nsweeps < 0) return -1;
+    int64_t N = (int64_t)L * L, K = N / 2;
+    for (int i = 0; i < nwin; ++i)
+        if (lo[i] < 0 || hi[i] > K || hi[i] - lo[i] < 1 || hi[i] - lo[i] + 1 > wmax) return -1;
+    orc_geom g = mkgeom(2, L, L, 1);
+    #pragma omp parallel for schedule(dynamic)
+    for (int64_t w = 0; w < (int64_t)nwin * M; ++w) {
+        int win = (int)(w / M);
+        if (active && !active[win]) continue;
+        int8_t *s = spins + w * N;
+        int64_t *Gw = G + w * wmax;
+        uint32_t *Hw = H + w * wmax;
+        int64_t klo = lo[win], khi = hi[win], k = (E[w] + 2 * N) / 4;
+        for (int t = 0; t < nsweeps; ++t) {
+            uint64_t sweep = sweep0 + (uint64_t)t;
+            for (int y = 0; y < L; ++y)
+                for (int x = 0; x < L; ++x) {
+                    int64_t i = site(&g, x, y, 0);
+                    int dl = 2 * s[i] * local_field(&g, s, NULL, x, y, 0) / 4;
+                    int64_t k2 = k + dl;
+                    int accept;
+                    if (dl == 0) accept = 1;
+                    else if (k2 < klo || k2 > khi) accept = 0;       /* counted again */
+                    else {
+                        int64_t d = Gw[k2 - klo] - Gw[k - klo];
+                        if (d <= 0) accept = 1;
+                        else {
+                            uint32_t r = orc_draw_word(seed, ORC_TAG_MUCA, (uint32_t)i, (uint32_t)w, sweep);
+                            accept = (uint64_t)r < orc_wl_threshold((uint64_t)d);
+                        }
+                    }
+                    if (accept) { s[i] = (int8_t)-s[i]; k = k2; }
+                    Gw[k - klo] += inc[win];
+                    Hw[k - klo] += 1u;
+                }
+        }
+        E[w] = 4 * k - 2 * N;
+        /* ln g is fixed up to a constant: the walker's estimate is shifted to a
+         * minimum of 0 over its levels with states (level 1 has none), which
+         * keeps it bounded and changes no decision */
+        int64_t mn = INT64_MAX;
+        for (int64_t kk = klo; kk <= khi; ++kk)
+            if (kk != 1 && Gw[kk - klo] < mn) mn = Gw[kk - klo];
+        for (int64_t kk = klo; kk <= khi; ++kk) Gw[kk - klo] -= mn;
+    }
     return 0;
 }

@@ -121,13 +121,32 @@ MUTANTS = [
      "if (((y / T) & 1) != P || ((x + y) & 1) != c) continue;"),
     ("dcb: odd sites first", "if (((x / T + y / T) & 1) != P || ((x + y) & 1) != c) continue;",
      "if (((x / T + y / T) & 1) != P || ((x + y + 1) & 1) != c) continue;"),
+    # Wang-Landau in windows (Sec. "Wang-Landau update", windows of Sec.
+    # "Multicanonical simulations")
+    ("wl: rejected out-of-window move not counted", "else if (k2 < klo || k2 > khi) accept = 0;       /* counted again */",
+     "else if (k2 < klo || k2 > khi) continue;"),
+    ("wl: acceptance ratio inverted", "int64_t d = Gw[k2 - klo] - Gw[k - klo];",
+     "int64_t d = Gw[k - klo] - Gw[k2 - klo];"),
+    ("wl: estimate raised before the move", "                    if (accept) { s[i] = (int8_t)-s[i]; k = k2; }\n"
+     "                    Gw[k - klo] += inc[win];",
+     "                    Gw[k - klo] += inc[win];\n                    if (accept) { s[i] = (int8_t)-s[i]; k = k2; }"),
+    ("wl: table factor for the wrong byte", "p = p * t16[(lo >> 16) & 255u];", "p = p * t16[(lo >> 8) & 255u];"),
+    ("wl: threshold floor", "    uint64_t T = (uint64_t)ceil(ldexp(p, 32));\n    return T < 1 ? 1 : T;",
+     "    uint64_t T = (uint64_t)floor(ldexp(p, 32));\n    return T < 1 ? 1 : T;"),
+    ("wl: drive ignores the draw", "if (r >> 31) { s[i] = (int8_t)-s[i]; k += dl; }",
+     "{ s[i] = (int8_t)-s[i]; k += dl; }"),
+    ("wl: match shift sign", "s = s + (prev[k - lo[i - 1]] - cur[k - lo[i]])",
+     "s = s + (cur[k - lo[i]] - prev[k - lo[i - 1]])", "oracle/__init__.py"),
+    ("wl: average without the min shift", "    avg -= min(int(avg[j]) for j in ks)\n", "", "oracle/__init__.py"),
+    ("wl: ln f not halved", "inc = [WL_ONE >> stage[i] for i in range(nwin)]", "inc = [WL_ONE for i in range(nwin)]",
+     "oracle/__init__.py"),
 ]
 
 PIN_TESTS = ["tests/test_golden_lng.py", "tests/test_oracle_dcb.py", "tests/test_oracle_exact.py",
              "tests/test_oracle_mlp.py",
              "tests/test_oracle_muca.py", "tests/test_oracle_pa.py", "tests/test_oracle_pt.py",
              "tests/test_oracle_rng.py", "tests/test_oracle_streams.py", "tests/test_oracle_sweep.py",
-             "tests/test_oracle_tables.py"]
+             "tests/test_oracle_tables.py", "tests/test_oracle_wl.py"]
 
 
 def _copy_tree(dst):
