@@ -55,6 +55,9 @@ def parse():
                         "taken with)")
     p.add_argument("--tune", action="store_true", help="pick the launch shape with the autotuner instead")
     p.add_argument("--no-rows", action="store_true", help="skip the other hot-path rows' throughput lines")
+    p.add_argument("--skip-rows", default="",
+                   help="comma-separated rows to leave out: mlp (the training graph, which a counter-collecting "
+                        "profiler run does not survive)")
     p.add_argument("--muca", default="64",
                    help="comma-separated test sizes (of 64,96,128) of the learned-vs-plain multicanonical "
                         "comparison added to the line (default 64, about a minute; 128 takes many minutes)")
@@ -124,7 +127,7 @@ def _events_ms(torch, fn, reps):
     return sorted(out)[len(out) // 2]
 
 
-def row_measurements(torch, mcs, ctx, dev):
+def row_measurements(torch, mcs, ctx, dev, skip=()):
     """Throughput of the other hot-path rows on their workloads' shapes, each
     timed with events around library calls (inputs resident in HBM), with the
     algorithmic bytes that an unfused sweep moves: int8 2 B per flip (+3 B of
@@ -326,6 +329,8 @@ def row_measurements(torch, mcs, ctx, dev):
                                       "ms_per_sweep": el * 250.0}
     del spins, E, wsm, H
 
+    if "mlp" in skip:
+        return rows
     # MLP for initial weights: full-batch Adam epochs (hand-written forward,
     # backward and update kernels, replayed graph) on a training set shaped
     # like the one of converged weights at L = 16, 24, 32, 48 (here the smooth
@@ -625,7 +630,7 @@ def main():
                       "L": L, "lattices": 3, "betas": list(BETAS), "sweeps_per_step": SWEEPS_PER_STEP},
            "roofline": roof, "valu": valu}
     if not a.no_rows:
-        out["rows"] = row_measurements(torch, mcs, ctx, dev)
+        out["rows"] = row_measurements(torch, mcs, ctx, dev, skip=[x for x in a.skip_rows.split(",") if x])
     if not a.no_muca and a.muca:
         out["muca"] = muca_comparison(torch, mcs, ctx, [int(x) for x in a.muca.split(",")], a.muca_prod)
         # the metric's second part: sweeps to a flat histogram, learned / plain

@@ -17,9 +17,10 @@ struct PaPop {
     int8_t *nxt;            // population after the step
     const int32_t *E;       // energies of cur
     int32_t *Enew;          // energies of nxt
-    double *x, *cmax;       // [R] scan scratch
+    double *rmx;            // [R] running maximum of each block's inclusive sums x
+    double *blk;            // [4][nb], nb = ceil(R / 64): block totals, largest x of each
+                            // block, block offsets G_q + B_b, running maximum of C at block ends
     int32_t *n, *newparent; // [R] copy numbers, parent of each new slot
-    int32_t *done;          // resampling workgroups finished in this step (0 between steps)
     int64_t *hist;          // [rows][N + 1]
     double *ctot;           // [nsteps]
 };

@@ -49,7 +49,7 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct PaLayout {
     size_t wtab = 0, total = 0;
-    std::vector<size_t> E, Enew, x, cmax, n, newparent, ctot, hist, done;
+    std::vector<size_t> E, Enew, rmx, blk, n, newparent, ctot, hist;
 };
 
 PaLayout pa_layout(const mc_pa_args *a)
@@ -64,13 +64,12 @@ PaLayout pa_layout(const mc_pa_args *a)
         const size_t R = (size_t)a->R, N = (size_t)a->L[p] * a->L[p];
         lay.E.push_back(off), off += align256(R * 4);
         lay.Enew.push_back(off), off += align256(R * 4);
-        lay.x.push_back(off), off += align256(R * 8);
-        lay.cmax.push_back(off), off += align256(R * 8);
+        lay.rmx.push_back(off), off += align256(R * 8);
+        lay.blk.push_back(off), off += align256((R + 63) / 64 * 4 * 8);
         lay.n.push_back(off), off += align256(R * 4);
         lay.newparent.push_back(off), off += align256(R * 4);
         lay.ctot.push_back(off), off += align256((size_t)std::max(1, a->nsteps) * 8);
         lay.hist.push_back(off), off += align256((size_t)(a->nsteps + 1) * (N + 1) * 8);
-        lay.done.push_back(off), off += 256;
     }
     lay.total = off;
     return lay;
@@ -155,15 +154,13 @@ int mc_pa_anneal(mc_ctx *ctx, const mc_pa_args *a, void *const *pop_spins, doubl
         P.G = pa_group_for(ctx, P.L);
         P.blk0 = blocks;
         blocks += (P.R + P.G - 1) / P.G;
-        P.x = (double *)(w + lay.x[p]);
-        P.cmax = (double *)(w + lay.cmax[p]);
+        P.rmx = (double *)(w + lay.rmx[p]);
+        P.blk = (double *)(w + lay.blk[p]);
         P.n = (int32_t *)(w + lay.n[p]);
         P.newparent = (int32_t *)(w + lay.newparent[p]);
         P.ctot = (double *)(w + lay.ctot[p]);
         P.hist = (int64_t *)(w + lay.hist[p]);
-        P.done = (int32_t *)(w + lay.done[p]);
         if (e == hipSuccess) e = launch_fill_i64(P.hist, (int64_t)(a->nsteps + 1) * (P.N + 1), 0, s);
-        if (e == hipSuccess) e = launch_fill_i64((int64_t *)P.done, 1, 0, s);
     }
     if (e == hipSuccess && a->step_first == 1)
         for (int p = 0; p < a->npop && e == hipSuccess; ++p) {
