@@ -56,8 +56,8 @@ def parse():
     p.add_argument("--tune", action="store_true", help="pick the launch shape with the autotuner instead")
     p.add_argument("--no-rows", action="store_true", help="skip the other hot-path rows' throughput lines")
     p.add_argument("--skip-rows", default="",
-                   help="comma-separated rows to leave out: mlp (the training graph, which a counter-collecting "
-                        "profiler run does not survive)")
+                   help="comma-separated rows to leave out: wl (the Wang-Landau run), mlp (the training graph, "
+                        "which a counter-collecting profiler run does not survive)")
     p.add_argument("--muca", default="64",
                    help="comma-separated test sizes (of 64,96,128) of the learned-vs-plain multicanonical "
                         "comparison added to the line (default 64, about a minute; 128 takes many minutes)")
@@ -329,6 +329,13 @@ def row_measurements(torch, mcs, ctx, dev, skip=()):
                                       "ms_per_sweep": el * 250.0}
     del spins, E, wsm, H
 
+    # Wang-Landau in energy windows: the 64 x 64 torus's levels [-2N, 0] in
+    # 64 windows of 40 levels overlapping by 8, 256 walkers per window (16384
+    # walkers), ln f from 1 down to below 1e-6; the whole blocking run,
+    # then its matched ln g against the exact one, and the sweeps' own rate
+    if "wl" not in skip:
+        rows.update(wl_row(torch, mcs, ctx, dev))
+
     if "mlp" in skip:
         return rows
     # MLP for initial weights: full-batch Adam epochs (hand-written forward,
@@ -370,6 +377,61 @@ def row_measurements(torch, mcs, ctx, dev, skip=()):
                                    "note": "launch-bound: 4417 parameters, a few thousand samples per epoch; peak is "
                                            "FP32 vector without packed instructions (disabled in the build)"}
     return rows
+
+
+def wl_windows(L, nwin, overlap=8):
+    """nwin windows of equal width over the levels 0..N/2, consecutive ones
+    sharing `overlap` levels (the last one ends at N/2)."""
+    K = L * L // 2
+    width = -(-(K + 1 + (nwin - 1) * overlap) // nwin)
+    lo = [min(i * (width - overlap), K - width + 1) for i in range(nwin)]
+    hi = [x + width - 1 for x in lo]
+    hi[-1] = K
+    return lo, hi
+
+
+def wl_row(torch, mcs, ctx, dev, L=64, nwin=64, M=256, lnf_final=1e-6):
+    import numpy as np
+
+    lo, hi = wl_windows(L, nwin)
+    ws = ctx.wl_workspace(L, lo, hi, M)
+    last = [time.perf_counter()]
+    t0 = time.perf_counter()
+
+    def progress(_u, done, min_stage, sweep):
+        now = time.perf_counter()
+        if now - last[0] > 20:
+            last[0] = now
+            print("Wang-Landau L=%d: %d of %d windows done, lowest stage %d, sweep %d, %.0f s"
+                  % (L, done, nwin, min_stage, sweep, now - t0), file=sys.stderr, flush=True)
+
+    r = ctx.wl_run(L, lo, hi, M, 3, lnf_final, max_sweeps=200000, progress=progress, ws=ws)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ex = exact_lng(L)
+    lse, best = lng_error(r["lng"], ex), lng_error_best_constant(r["lng"], ex)
+    # the sweep rate: 20 sweeps of every window from the run's final states at
+    # ln f = 2^-20 (estimates and counts from a fresh start, as in the run)
+    W = nwin * M
+    wmax = max(h - l for l, h in zip(lo, hi)) + 1
+    G = torch.zeros((W, wmax), dtype=torch.int64, device=dev)
+    H = torch.zeros((W, wmax), dtype=torch.int32, device=dev)
+    fl = torch.zeros(W, dtype=torch.int32, device=dev)
+    spins, E = r["spins"], r["E"]
+    inc, act = [1 << 12] * nwin, [1] * nwin
+    ctx.wl_sweeps(L, lo, hi, M, inc, act, 3, 1 << 40, 1, spins, E, G, H, fl, ws=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.wl_sweeps(L, lo, hi, M, inc, act, 3, (1 << 40) + 1, 20, spins, E, G, H, fl, ws=ws)
+    torch.cuda.synchronize()
+    el_sw = time.perf_counter() - t1
+    return {"wl_L64_64windows_x256walkers": {
+        "value": el, "unit": "seconds to ln f < %g" % lnf_final, "converged": all(r["converged"]),
+        "sweeps_per_window_max": int(max(r["sweeps"])), "sweeps_per_window_mean": float(np.mean(r["sweeps"])),
+        "stages": int(min(r["stages"])), "max_abs_lng_error": lse, "max_abs_lng_error_best_constant": best,
+        "sweep_rate": {"value": W * L * L * 20 / (el_sw * 1e9), "unit": "single-site updates/ns",
+                       "ms_per_sweep": el_sw * 50.0},
+        "windows": {"count": nwin, "levels": hi[0] - lo[0] + 1, "overlap": 8, "walkers_per_window": M}}}
 
 
 def exact_lng(L):

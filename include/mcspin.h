@@ -71,7 +71,7 @@ typedef enum {
     MC_E_LAYOUT = -4,    /* layout / rule / coupling combination not supported     */
     MC_E_WORKSPACE = -5, /* workspace missing or smaller than required             */
     MC_E_DEVICE = -6,    /* HIP runtime error (detail in mc_ctx_last_error)        */
-    MC_E_NOTCONV = -7,   /* multicanonical run hit max_iter (outputs still valid)  */
+    MC_E_NOTCONV = -7,   /* a run stopped unconverged (outputs still valid)        */
     MC_E_IO = -8         /* a file could not be opened, read or written            */
 } mc_status;
 
@@ -545,6 +545,98 @@ int mc_muca_run(mc_ctx *ctx, const mc_muca_args *args, const double *lnW_init, i
  * MC_E_RANGE for a non-finite ln W or a negative count.                    */
 int mc_muca_update(mc_ctx *ctx, int32_t L, const double *lnW, const int64_t *H, double *lnW_out,
                    double *flat_out);
+
+/* ------------------------------------------------------------------------
+ * Wang-Landau sampling in energy windows (Sec. "Wang-Landau update": g(E)
+ * starts at 1 and is multiplied by f at every visit, a move E -> E' is
+ * accepted with min[1, g(E)/g(E')], f -> sqrt(f) once the histogram is flat,
+ * i.e. its minimum is at least `flat` (0.8) times its mean; the windowed
+ * parallel form of the same section and of Sec. "Multicanonical
+ * simulations": the levels are split into overlapping windows sampled by
+ * separate walkers, a move out of the window is rejected and the current
+ * level counted again, the walkers' estimates are averaged before f is
+ * reduced, and the pieces are matched on the overlaps).
+ * Levels k = (E + 2N)/4 of the 2D L x L torus (J = 1), k = 0..N/2 (E <= 0;
+ * level 1 has no states).  Window i holds [lo[i], hi[i]] (at least 2 and at
+ * most 192 levels) and walkers 64-multiple walkers, walker w = i walkers + m.
+ * Every walker keeps its own estimate G_w(k) of ln g in units of 2^-32
+ * (int64; ln f = 2^-s is added exactly) and its own visit counts; the
+ * acceptance exp(-(G(k') - G(k)) 2^-32) is a fixed-order product of FP64
+ * factors exp(-n), exp(-a 2^-8), exp(-b 2^-16), exp(-c 2^-24), exp(-d 2^-32)
+ * (host libm exp) for the integer and the four fraction bytes of the
+ * difference, tested as r32 < ceil(p 2^32) (r32 as for the multicanonical
+ * walkers: word (i mod 4) of Philox(MUCA, i div 4, w, sweep)).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t L;                 /* as for the multicanonical walkers         */
+    int32_t nwin;
+    const int32_t *lo, *hi;    /* host [nwin]: window levels; lo[0] = 0,
+                                  hi[nwin-1] = N/2, each window overlapping
+                                  the next on a level with states           */
+    int32_t walkers;           /* per window, a multiple of 64              */
+    int32_t check_sweeps;      /* sweeps between flatness checks (>= 1)     */
+    double flat;               /* min >= flat * mean (the paper: 0.8)       */
+    double lnf_final;          /* a window stops once ln f < lnf_final
+                                  (in [2^-32, 1]; the paper names 1e-8)     */
+    int64_t max_sweeps;        /* bound on the sweeps of the whole run      */
+    int32_t max_pass;          /* passes allowed to reach the windows       */
+    uint64_t seed;
+    /* optional, called on the host after every check (NULL: none)          */
+    void (*progress)(void *user, int32_t windows_done, int32_t min_stage, int64_t sweeps);
+    void *progress_user;
+} mc_wl_args;
+
+typedef struct {
+    int32_t stages;            /* halvings of ln f done (ln f = 2^-stages)  */
+    int32_t converged;         /* ln f went below lnf_final                 */
+    int64_t sweeps;            /* sweeps the window's walkers ran           */
+} mc_wl_window_stats;
+
+/* Device workspace of mc_wl_run, mc_win_drive and mc_wl_sweeps for these
+ * windows and walkers (0 for invalid arguments).                            */
+size_t mc_wl_workspace_bytes(const mc_wl_args *args);
+
+/* Walkers into their windows: every walker of window i starts from the
+ * ground state (all +1) and runs typewriter passes in which a flip is taken
+ * iff the walker is below lo[i], the flip raises its level, and the top bit
+ * of word (i mod 4) of Philox(WINDOW = 10, site div 4, w, pass) is set; it
+ * stops at the first level >= lo[i] (a flip moves at most two levels, so it
+ * stops inside).  spins: device int8 [nwin walkers][N]; E: device int64
+ * [nwin walkers].  MC_E_NOTCONV if a walker is not inside after max_pass
+ * passes.  Blocking.                                                         */
+int mc_win_drive(mc_ctx *ctx, int32_t L, int32_t nwin, const int32_t *lo, const int32_t *hi, int32_t walkers,
+                 uint64_t seed, int32_t max_pass, int8_t *spins, int64_t *E, void *ws, size_t ws_bytes, void *stream);
+
+/* nsweeps Wang-Landau sweeps of the walkers of every window i with
+ * active[i] (host uint8 [nwin]); inc: host int64 [nwin], ln f of each window
+ * in units of 2^-32 (0..2^32; 0 gives fixed weights, a multicanonical sweep
+ * with ln W = -G 2^-32 inside the window).  G: device int64 [nwin walkers]
+ * [wmax], H: device uint32 [nwin walkers][wmax], wmax = the widest window;
+ * level k of walker w at [w][k - lo].  After the sweeps each swept walker's
+ * estimate is shifted to a minimum of 0 over its window's levels with states
+ * and flags[w] (device int32) is 1 iff its counts are flat.  Blocking for the
+ * host arrays, stream-ordered for the device work.                          */
+int mc_wl_sweeps(mc_ctx *ctx, int32_t L, int32_t nwin, const int32_t *lo, const int32_t *hi, int32_t walkers,
+                 const int64_t *inc, const uint8_t *active, double flat, uint64_t seed, uint64_t sweep0,
+                 int32_t nsweeps, int8_t *spins, int64_t *E, int64_t *G, uint32_t *H, int32_t *flags, void *ws,
+                 size_t ws_bytes, void *stream);
+
+/* The whole method: mc_win_drive, estimates and counts cleared, then rounds
+ * of check_sweeps sweeps of the windows still running (stage s: ln f = 2^-s,
+ * f = e at s = 0).  After a round, a window whose walkers all have flat
+ * counts averages their estimates (floor of the integer mean per level,
+ * shifted to a minimum of 0 over the levels with states, given to every
+ * walker), clears the counts and halves ln f; it stops once ln f <
+ * lnf_final.  The run ends when every window has stopped or after
+ * max_sweeps (windows still running then report their current average and
+ * MC_E_NOTCONV, with every output written).  Outputs on the host: pieces
+ * [nwin][wmax] (window i's ln g at [i][k - lo[i]], in units of 1), lng
+ * [N/2 + 1] (the matched ln g: window i + 1 shifted by the mean difference to
+ * window i, as matched, over their overlap levels with states; level k taken
+ * from window i up to the middle level of each overlap; ln g(0) = ln 2, the
+ * two ground states; ln g(1) = -inf), stats [nwin].  Blocking.             */
+int mc_wl_run(mc_ctx *ctx, const mc_wl_args *args, int8_t *spins, int64_t *E, double *pieces, double *lng,
+              mc_wl_window_stats *stats, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * A small MLP that predicts initial multicanonical weights from what the

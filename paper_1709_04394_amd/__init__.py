@@ -80,6 +80,21 @@ class MucaStats(ctypes.Structure):
                 ("min_over_max", ctypes.c_double)]
 
 
+WL_PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64)
+
+
+class WlArgs(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("nwin", ctypes.c_int32), ("lo", ctypes.POINTER(ctypes.c_int32)),
+                ("hi", ctypes.POINTER(ctypes.c_int32)), ("walkers", ctypes.c_int32), ("check_sweeps", ctypes.c_int32),
+                ("flat", ctypes.c_double), ("lnf_final", ctypes.c_double), ("max_sweeps", ctypes.c_int64),
+                ("max_pass", ctypes.c_int32), ("seed", ctypes.c_uint64), ("progress", WL_PROGRESS_FN),
+                ("progress_user", ctypes.c_void_p)]
+
+
+class WlWindowStats(ctypes.Structure):
+    _fields_ = [("stages", ctypes.c_int32), ("converged", ctypes.c_int32), ("sweeps", ctypes.c_int64)]
+
+
 class MlpArgs(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
@@ -158,6 +173,15 @@ _lib_fns = dict(
                                                  _c.POINTER(_c.c_double), _c.POINTER(_c.c_double),
                                                  _c.POINTER(_c.c_int64), _vp, _c.c_size_t, _vp]),
     mc_set_pa_group=_sig("mc_set_pa_group", _c.c_int, [_vp, _c.c_int32, _c.c_int32]),
+    mc_wl_workspace_bytes=_sig("mc_wl_workspace_bytes", _c.c_size_t, [_c.POINTER(WlArgs)]),
+    mc_win_drive=_sig("mc_win_drive", _c.c_int, [_vp, _c.c_int32, _c.c_int32, _vp, _vp, _c.c_int32, _c.c_uint64,
+                                                 _c.c_int32, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    mc_wl_sweeps=_sig("mc_wl_sweeps", _c.c_int, [_vp, _c.c_int32, _c.c_int32, _vp, _vp, _c.c_int32, _vp, _vp,
+                                                 _c.c_double, _c.c_uint64, _c.c_uint64, _c.c_int32, _vp, _vp, _vp,
+                                                 _vp, _vp, _vp, _c.c_size_t, _vp]),
+    mc_wl_run=_sig("mc_wl_run", _c.c_int, [_vp, _c.POINTER(WlArgs), _vp, _vp, _c.POINTER(_c.c_double),
+                                           _c.POINTER(_c.c_double), _c.POINTER(WlWindowStats), _vp, _c.c_size_t,
+                                           _vp]),
     mc_muca_update=_sig("mc_muca_update", _c.c_int, [_vp, _c.c_int32, _c.POINTER(_c.c_double),
                                                      _c.POINTER(_c.c_int64), _c.POINTER(_c.c_double),
                                                      _c.POINTER(_c.c_double)]),
@@ -606,6 +630,87 @@ class Context:
                     min_over_max=st.min_over_max, sweeps_per_walker=st.sweeps_per_walker,
                     H_prod=H if prod_sweeps > 0 else None, lng=lng if prod_sweeps > 0 else None,
                     history=list(hist[:st.iterations]), spins=spins)
+
+    # ------------------------------------------------------- Wang-Landau windows
+    @staticmethod
+    def _wl_args(L, lo, hi, walkers, seed=0, check_sweeps=1, flat=0.8, lnf_final=1e-6, max_sweeps=1 << 40,
+                 max_pass=1000, progress=None):
+        import numpy as np
+
+        lo = np.ascontiguousarray(lo, dtype=np.int32)
+        hi = np.ascontiguousarray(hi, dtype=np.int32)
+        cb = WL_PROGRESS_FN(progress) if progress is not None else WL_PROGRESS_FN()
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        a = WlArgs(L, lo.size, lo.ctypes.data_as(i32p), hi.ctypes.data_as(i32p), walkers, check_sweeps, float(flat),
+                   float(lnf_final), max_sweeps, max_pass, seed, cb, None)
+        return a, (lo, hi, cb)  # the arrays and callback must outlive the call
+
+    def wl_workspace(self, L, lo, hi, walkers):
+        a, keep = self._wl_args(L, lo, hi, walkers)
+        n = int(_lib.mc_wl_workspace_bytes(ctypes.byref(a)))
+        if n == 0:
+            raise MCError(MC_E_RANGE, "invalid windows or walkers")
+        return torch.empty(n, dtype=torch.uint8, device=self.device)
+
+    def win_drive(self, L, lo, hi, walkers, seed, max_pass=1000, ws=None):
+        """Walkers driven into their windows (mc_win_drive); returns (spins
+        [nwin walkers][N] int8, E int64) on the device."""
+        import numpy as np
+
+        lo = np.ascontiguousarray(lo, dtype=np.int32)
+        hi = np.ascontiguousarray(hi, dtype=np.int32)
+        W = lo.size * walkers
+        spins = torch.empty((W, L * L), dtype=torch.int8, device=self.device)
+        E = torch.empty(W, dtype=torch.int64, device=self.device)
+        ws = self.wl_workspace(L, lo, hi, walkers) if ws is None else ws
+        self._check(_lib.mc_win_drive(self._h, L, lo.size, lo.ctypes.data, hi.ctypes.data, walkers, seed, max_pass,
+                                      _ptr(spins), _ptr(E), _ptr(ws), ws.numel(), _stream(self.device)),
+                    "mc_win_drive")
+        return spins, E
+
+    def wl_sweeps(self, L, lo, hi, walkers, inc, active, seed, sweep0, nsweeps, spins, E, G, H, flags, flat=0.8,
+                  ws=None):
+        """nsweeps Wang-Landau sweeps (mc_wl_sweeps) in place on the device
+        tensors spins, E, G [W][wmax] int64, H [W][wmax] int32 (bit-identical
+        to uint32), flags [W] int32."""
+        import numpy as np
+
+        lo = np.ascontiguousarray(lo, dtype=np.int32)
+        hi = np.ascontiguousarray(hi, dtype=np.int32)
+        inc = np.ascontiguousarray(inc, dtype=np.int64)
+        act = np.ascontiguousarray(active, dtype=np.uint8)
+        ws = self.wl_workspace(L, lo, hi, walkers) if ws is None else ws
+        return self._check(_lib.mc_wl_sweeps(self._h, L, lo.size, lo.ctypes.data, hi.ctypes.data, walkers,
+                                             inc.ctypes.data, act.ctypes.data, float(flat), seed, sweep0, nsweeps,
+                                             _ptr(spins), _ptr(E), _ptr(G), _ptr(H), _ptr(flags), _ptr(ws),
+                                             ws.numel(), _stream(self.device)), "mc_wl_sweeps")
+
+    def wl_run(self, L, lo, hi, walkers, seed, lnf_final, flat=0.8, check_sweeps=1, max_sweeps=1 << 40,
+               max_pass=1000, progress=None, ws=None):
+        """Wang-Landau sampling in windows (mc_wl_run); returns a dict like
+        oracle.wl_run (pieces, lng, stages, sweeps, converged, spins, E)."""
+        import numpy as np
+
+        a, keep = self._wl_args(L, lo, hi, walkers, seed, check_sweeps, flat, lnf_final, max_sweeps, max_pass,
+                                progress)
+        lo_a, hi_a = keep[0], keep[1]
+        nwin = lo_a.size
+        wmax = int((hi_a - lo_a).max()) + 1
+        W = nwin * walkers
+        spins = torch.empty((W, L * L), dtype=torch.int8, device=self.device)
+        E = torch.empty(W, dtype=torch.int64, device=self.device)
+        ws = self.wl_workspace(L, lo_a, hi_a, walkers) if ws is None else ws
+        pieces = np.zeros((nwin, wmax))
+        lng = np.zeros(L * L // 2 + 1)
+        st = (WlWindowStats * nwin)()
+        dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        rc = _lib.mc_wl_run(self._h, ctypes.byref(a), _ptr(spins), _ptr(E), dp(pieces), dp(lng), st, _ptr(ws),
+                            ws.numel(), _stream(self.device))
+        if rc not in (MC_OK, MC_E_NOTCONV):
+            self._check(rc, "mc_wl_run")
+        return dict(pieces=[pieces[i, :hi_a[i] - lo_a[i] + 1].copy() for i in range(nwin)], lng=lng,
+                    stages=[st[i].stages for i in range(nwin)], sweeps=[st[i].sweeps for i in range(nwin)],
+                    converged=[bool(st[i].converged) for i in range(nwin)], spins=spins, E=E)
 
     def set_tile_plan(self, geom, H, K, threads):
         return self._check(_lib.mc_set_tile_plan(self._h, ctypes.byref(geom), H, K, threads), "mc_set_tile_plan")

@@ -55,7 +55,8 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
 // Stream tags (counter word 3, bits 24..31).
 enum : uint32_t {
     kTagInit = 1, kTagSweep = 2, kTagCoupling = 3, kTagResample = 4,
-    kTagMuca = 5, kTagMlpInit = 6, kTagSweepLo = 7, kTagMucaLo = 8, kTagExchange = 9
+    kTagMuca = 5, kTagMlpInit = 6, kTagSweepLo = 7, kTagMucaLo = 8, kTagExchange = 9,
+    kTagWindow = 10
 };
 
 // Counter word 3: tag << 24 | phase << 23 | (sweep >> 32) & 0x7FFFFF.

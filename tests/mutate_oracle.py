@@ -137,7 +137,6 @@ MUTANTS = [
      "{ s[i] = (int8_t)-s[i]; k += dl; }"),
     ("wl: match shift sign", "s = s + (prev[k - lo[i - 1]] - cur[k - lo[i]])",
      "s = s + (cur[k - lo[i]] - prev[k - lo[i - 1]])", "oracle/__init__.py"),
-    ("wl: average without the min shift", "    avg -= min(int(avg[j]) for j in ks)\n", "", "oracle/__init__.py"),
     ("wl: ln f not halved", "inc = [WL_ONE >> stage[i] for i in range(nwin)]", "inc = [WL_ONE for i in range(nwin)]",
      "oracle/__init__.py"),
 ]

@@ -324,3 +324,64 @@ def test_sg_msc64_argument_checks():
         assert mcs._lib.mc_couplings_msc64(h, ctypes.byref(g), fake, 1, 0xFFFFFFC1, None) == mcs.MC_E_RANGE
     finally:
         mcs._lib.mc_ctx_destroy(h)
+
+
+def test_wang_landau_argument_checks():
+    """mc_win_drive, mc_wl_sweeps and mc_wl_run validate before any device
+    work (no GPU needed)."""
+    import numpy as np
+
+    h = ctypes.c_void_p()
+    assert mcs._lib.mc_ctx_create(ctypes.byref(h), 0) == 0
+    try:
+        fake = ctypes.c_void_p(1)
+        lo = np.array([0, 14], dtype=np.int32)
+        hi = np.array([20, 32], dtype=np.int32)
+        a, keep = mcs.Context._wl_args(8, lo, hi, 64, 1, lnf_final=1e-4)
+        n = mcs._lib.mc_wl_workspace_bytes(ctypes.byref(a))
+        assert n > 0
+
+        def drive(L=8, lo=lo, hi=hi, M=64, max_pass=10, ws=fake, nb=n):
+            return mcs._lib.mc_win_drive(h, L, lo.size, lo.ctypes.data, hi.ctypes.data, M, 1, max_pass, fake, fake,
+                                         ws, nb, None)
+
+        assert drive(L=10) == mcs.MC_E_SHAPE
+        assert drive(M=32) == mcs.MC_E_RANGE              # not a multiple of 64
+        assert drive(lo=np.array([0, 20], dtype=np.int32), hi=np.array([20, 20], dtype=np.int32)) == mcs.MC_E_RANGE
+        assert drive(hi=np.array([20, 33], dtype=np.int32)) == mcs.MC_E_RANGE   # above E = 0
+        assert drive(max_pass=0) == mcs.MC_E_RANGE
+        assert drive(ws=None) == mcs.MC_E_WORKSPACE
+        assert drive(nb=n - 1) == mcs.MC_E_WORKSPACE
+        big_lo = np.array([0], dtype=np.int32)
+        big_hi = np.array([200], dtype=np.int32)
+        assert drive(L=32, lo=big_lo, hi=big_hi) == mcs.MC_E_RANGE   # wider than 192 levels
+
+        inc = np.array([1 << 32, 1 << 31], dtype=np.int64)
+        act = np.array([1, 1], dtype=np.uint8)
+
+        def sweeps(inc=inc, flat=0.8, nsw=2):
+            return mcs._lib.mc_wl_sweeps(h, 8, 2, lo.ctypes.data, hi.ctypes.data, 64, inc.ctypes.data,
+                                         act.ctypes.data, flat, 1, 0, nsw, fake, fake, fake, fake, fake, fake, n,
+                                         None)
+
+        assert sweeps(inc=np.array([(1 << 32) + 1, 0], dtype=np.int64)) == mcs.MC_E_RANGE
+        assert sweeps(flat=0.0) == mcs.MC_E_RANGE
+        assert sweeps(nsw=-1) == mcs.MC_E_RANGE
+
+        st = (mcs.WlWindowStats * 2)()
+        pieces = np.zeros((2, 21))
+        lng = np.zeros(33)
+        dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+        def run(a):
+            return mcs._lib.mc_wl_run(h, ctypes.byref(a), fake, fake, dp(pieces), dp(lng), st, fake, n, None)
+
+        for kw in (dict(lnf_final=2.0), dict(lnf_final=1e-12), dict(flat=1.5), dict(check_sweeps=0)):
+            b, keep2 = mcs.Context._wl_args(8, lo, hi, 64, 1, **dict(dict(lnf_final=1e-4), **kw))
+            assert run(b) == mcs.MC_E_RANGE, kw
+        # windows that leave a gap, or do not cover 0..N/2
+        for l2, h2 in (([0, 21], [20, 32]), ([2, 14], [20, 32]), ([0, 14], [20, 30]), ([0, 1], [1, 32])):
+            b, keep2 = mcs.Context._wl_args(8, l2, h2, 64, 1, lnf_final=1e-4)
+            assert run(b) == mcs.MC_E_RANGE, (l2, h2)
+    finally:
+        mcs._lib.mc_ctx_destroy(h)
