@@ -611,3 +611,67 @@ def wl_run(L, lo, hi, M, seed, lnf_final, flat=0.8, check=1, max_sweeps=1 << 30,
         pieces.append(G[i * M, :n].astype(np.float64) / float(WL_ONE))
     return dict(pieces=pieces, lng=wl_match(lo, hi, pieces, K), stages=stage, sweeps=sweeps,
                 converged=[not a for a in active], spins=spins, E=E, G=G, H=H, sweep=sweep)
+
+
+# ------------------------------------------------ multicanonical in windows
+def muca_windows_run(L, lo, hi, M, seed, rec_sweeps, max_iter, flat=0.8, eq_sweeps=2, max_pass=1000):
+    """The multicanonical recursion in windows (Sec. "Multicanonical
+    simulations": the range split into windows simulated separately, a move
+    out of the window rejected and the current state counted again, flat
+    weights to start, the weight recursion, neighbouring pieces matched on
+    their overlaps).  Walkers are driven into their windows; each window's
+    weights are ln W = -G 2^-32 with G integer (start 0), held by all its
+    walkers.  An iteration of a window still running: eq_sweeps unrecorded
+    and rec_sweeps recorded multicanonical sweeps (wl_sweeps with ln f = 0),
+    the walkers' counts added into H; the window stops once min H >= flat *
+    max H over its levels with states, its piece being ln g = ln H + G 2^-32
+    of that iteration; otherwise G += floor(ln H 2^32 + 1/2) where H > 0
+    (ln W <- ln W - ln H), shifted to a minimum of 0.  Windows not flat after
+    max_iter iterations give their last weights' -ln W = G 2^-32.  Returns the
+    pieces, the matched ln g (wl_match), and per window the iterations run
+    and whether it became flat."""
+    lo, hi, wmax = _windows(lo, hi)
+    nwin = lo.size
+    K = L * L // 2
+    spins, E = win_drive(L, lo, hi, M, seed, max_pass)
+    G = np.zeros((nwin * M, wmax), dtype=np.int64)
+    H = np.zeros((nwin * M, wmax), dtype=np.uint32)
+    active = [1] * nwin
+    iters = [0] * nwin
+    pieces = [None] * nwin
+    zero = [0] * nwin
+    sweep = 0
+    for _ in range(max_iter):
+        if not any(active):
+            break
+        wl_sweeps(L, lo, hi, M, zero, active, seed, sweep, eq_sweeps, spins, E, G, H)
+        sweep += eq_sweeps
+        H[:] = 0
+        wl_sweeps(L, lo, hi, M, zero, active, seed, sweep, rec_sweeps, spins, E, G, H)
+        sweep += rec_sweeps
+        for i in range(nwin):
+            if not active[i]:
+                continue
+            iters[i] += 1
+            n = hi[i] - lo[i] + 1
+            Hw = [sum(int(v) for v in H[i * M:(i + 1) * M, j]) for j in range(n)]
+            ks = [k - lo[i] for k in wl_levels_with_states(lo[i], hi[i])]
+            g = G[i * M, :n]
+            if float(min(Hw[j] for j in ks)) >= flat * float(max(Hw[j] for j in ks)):
+                pieces[i] = np.array([math.log(float(Hw[j])) + float(g[j]) / float(WL_ONE) if Hw[j] > 0 else 0.0
+                                      for j in range(n)])
+                active[i] = 0
+                continue
+            new = g.copy()
+            for j in range(n):
+                if Hw[j] > 0:
+                    new[j] += math.floor(math.log(float(Hw[j])) * float(WL_ONE) + 0.5)
+            new -= min(int(new[j]) for j in ks)
+            G[i * M:(i + 1) * M, :n] = new
+    for i in range(nwin):
+        if pieces[i] is None:
+            # not flat: the last recursion's weights, -ln W = G 2^-32
+            n = hi[i] - lo[i] + 1
+            pieces[i] = G[i * M, :n].astype(np.float64) / float(WL_ONE)
+    return dict(pieces=pieces, lng=wl_match(lo, hi, pieces, K), iterations=iters,
+                converged=[not a for a in active], spins=spins, E=E, G=G, sweep=sweep)

@@ -139,6 +139,10 @@ MUTANTS = [
      "s = s + (cur[k - lo[i]] - prev[k - lo[i - 1]])", "oracle/__init__.py"),
     ("wl: ln f not halved", "inc = [WL_ONE >> stage[i] for i in range(nwin)]", "inc = [WL_ONE for i in range(nwin)]",
      "oracle/__init__.py"),
+    ("muca windows: recursion sign", "new[j] += math.floor(math.log(float(Hw[j])) * float(WL_ONE) + 0.5)",
+     "new[j] -= math.floor(math.log(float(Hw[j])) * float(WL_ONE) + 0.5)", "oracle/__init__.py"),
+    ("muca windows: piece without the weights", "pieces[i] = np.array([math.log(float(Hw[j])) + float(g[j]) / float(WL_ONE) if Hw[j] > 0 else 0.0\n                                      for j in range(n)])",
+     "pieces[i] = np.array([math.log(float(Hw[j])) if Hw[j] > 0 else 0.0\n                                      for j in range(n)])", "oracle/__init__.py"),
 ]
 
 PIN_TESTS = ["tests/test_golden_lng.py", "tests/test_oracle_dcb.py", "tests/test_oracle_exact.py",

@@ -14,6 +14,8 @@
   each, ln f down to 1e-4, matched ln g within 0.1 of the exact one.
 * Matching: pieces of the exact ln g shifted by arbitrary constants are put
   back together exactly.
+* The multicanonical recursion in windows (flat start, ln W -= ln H per
+  window, count-again, matching) converges to the exact g(E) at L = 8 and 16.
 * Stream contract: a tiny case rebuilt site by site from the pinned Philox
   draws and the threshold (typewriter order, draw index, count-again, visit
   and estimate updates after every attempt, the estimate shifted to a
@@ -184,3 +186,13 @@ def test_stream_contract_rebuilt_site_by_site():
         assert 4 * k - 2 * N == E[w]
         G_ref[w] -= G_ref[w].min()  # the call ends with the estimate's minimum at 0
     assert np.array_equal(G_ref, G) and np.array_equal(H_ref, H)
+
+
+@pytest.mark.parametrize("L,lo,hi,rec,tol", [(8, [0, 14], [20, 32], 200, 0.15), (16, [0, 40, 90], [60, 110, 128], 1000, 0.15)])
+def test_windowed_multicanonical_converges(L, lo, hi, rec, tol):
+    ex = _exact_levels(L)
+    r = oracle.muca_windows_run(L, lo, hi, 64, 5, rec, 100)
+    assert all(r["converged"])
+    m = np.isfinite(ex)
+    err = np.max(np.abs(r["lng"][m] - ex[m]))
+    assert err < tol, err
