@@ -240,10 +240,16 @@ def row_measurements(torch, mcs, ctx, dev, skip=()):
 
         ms = _events_ms(torch, run_dcb, 3)
         fpn = 3.0 * L * L * kh * nsw / (ms * 1e6)
+        # the kernel's own algorithmic bytes: the packed lattice read and
+        # written once per sweep (2 bits per site), i.e. 0.25 / k B per
+        # attempted update; far below HBM speed, the kernel is bound by VALU
+        # issue at k >= 10 and by its per-launch latency at k = 1
+        bpu = 0.25 / kh
         rows["dcb_4096x3_T128_k%d" % kh] = {"value": fpn, "unit": "spin flips/ns", "ms_per_sweep": ms / nsw,
                                           "hits": kh, "tile": 128,
-                                          "roofline": {"bound": "hbm", "achieved": fpn * 2.0, "peak": HBM_PEAK_GBS,
-                                                       "unit": "GB/s", "frac": fpn * 2.0 / HBM_PEAK_GBS}}
+                                          "roofline": {"bound": "hbm", "achieved": fpn * bpu, "peak": HBM_PEAK_GBS,
+                                                       "unit": "GB/s", "frac": fpn * bpu / HBM_PEAK_GBS,
+                                                       "bytes_per_update": bpu}}
     del lat1, wsd
 
     # population annealing: 4 populations x 16384 replicas, L in {16, 32, 64, 128},

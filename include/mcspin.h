@@ -638,6 +638,38 @@ int mc_wl_sweeps(mc_ctx *ctx, int32_t L, int32_t nwin, const int32_t *lo, const 
 int mc_wl_run(mc_ctx *ctx, const mc_wl_args *args, int8_t *spins, int64_t *E, double *pieces, double *lng,
               mc_wl_window_stats *stats, void *ws, size_t ws_bytes, void *stream);
 
+/* The multicanonical recursion in the same windows (Sec. "Multicanonical
+ * simulations": windows simulated separately from flat weights, the
+ * count-again rule, Eq. weight_modification, pieces matched on overlaps).
+ * Walkers are driven into their windows (mc_win_drive); each window's
+ * weights ln W = -G 2^-32 (G integer, start 0) are held by all its walkers.
+ * An iteration of every window still running: eq_sweeps unrecorded and
+ * rec_sweeps recorded sweeps (mc_wl_sweeps with ln f = 0), the walkers'
+ * counts pooled into H; the window stops once min H >= flat * max H over its
+ * levels with states (its piece: ln g = ln H + G 2^-32, 0 where H = 0);
+ * otherwise G += floor(ln H 2^32 + 1/2) where H > 0 (host libm log), shifted
+ * to a minimum of 0 over the levels with states.  Windows not flat after
+ * max_iter iterations give -ln W = G 2^-32 of their last weights, and the call
+ * returns MC_E_NOTCONV with every output written.  pieces, lng, windows and
+ * matching as for mc_wl_run; stats [nwin].  Blocking.                       */
+typedef struct {
+    int32_t L, nwin;
+    const int32_t *lo, *hi;    /* host [nwin], as for mc_wl_run             */
+    int32_t walkers;           /* per window, a multiple of 64              */
+    int32_t eq_sweeps, rec_sweeps, max_iter;
+    double flat;               /* min/max of the pooled counts (0.8)        */
+    int32_t max_pass;
+    uint64_t seed;
+    void (*progress)(void *user, int32_t windows_done, int32_t iteration, int64_t sweeps);
+    void *progress_user;
+} mc_muca_win_args;
+
+typedef struct { int32_t iterations, converged; } mc_muca_win_stats;
+
+size_t mc_muca_windows_workspace_bytes(const mc_muca_win_args *args);
+int mc_muca_windows_run(mc_ctx *ctx, const mc_muca_win_args *args, int8_t *spins, int64_t *E, double *pieces,
+                        double *lng, mc_muca_win_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------------
  * A small MLP that predicts initial multicanonical weights from what the
  * method itself produced at smaller L: x = (E/N + 1, 32/L - 1) -> tanh(64)

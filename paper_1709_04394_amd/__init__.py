@@ -95,6 +95,18 @@ class WlWindowStats(ctypes.Structure):
     _fields_ = [("stages", ctypes.c_int32), ("converged", ctypes.c_int32), ("sweeps", ctypes.c_int64)]
 
 
+class MucaWinArgs(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("nwin", ctypes.c_int32), ("lo", ctypes.POINTER(ctypes.c_int32)),
+                ("hi", ctypes.POINTER(ctypes.c_int32)), ("walkers", ctypes.c_int32), ("eq_sweeps", ctypes.c_int32),
+                ("rec_sweeps", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("flat", ctypes.c_double),
+                ("max_pass", ctypes.c_int32), ("seed", ctypes.c_uint64), ("progress", WL_PROGRESS_FN),
+                ("progress_user", ctypes.c_void_p)]
+
+
+class MucaWinStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32)]
+
+
 class MlpArgs(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
@@ -182,6 +194,10 @@ _lib_fns = dict(
     mc_wl_run=_sig("mc_wl_run", _c.c_int, [_vp, _c.POINTER(WlArgs), _vp, _vp, _c.POINTER(_c.c_double),
                                            _c.POINTER(_c.c_double), _c.POINTER(WlWindowStats), _vp, _c.c_size_t,
                                            _vp]),
+    mc_muca_windows_workspace_bytes=_sig("mc_muca_windows_workspace_bytes", _c.c_size_t, [_c.POINTER(MucaWinArgs)]),
+    mc_muca_windows_run=_sig("mc_muca_windows_run", _c.c_int, [_vp, _c.POINTER(MucaWinArgs), _vp, _vp,
+                                                               _c.POINTER(_c.c_double), _c.POINTER(_c.c_double),
+                                                               _c.POINTER(MucaWinStats), _vp, _c.c_size_t, _vp]),
     mc_muca_update=_sig("mc_muca_update", _c.c_int, [_vp, _c.c_int32, _c.POINTER(_c.c_double),
                                                      _c.POINTER(_c.c_int64), _c.POINTER(_c.c_double),
                                                      _c.POINTER(_c.c_double)]),
@@ -710,6 +726,40 @@ class Context:
             self._check(rc, "mc_wl_run")
         return dict(pieces=[pieces[i, :hi_a[i] - lo_a[i] + 1].copy() for i in range(nwin)], lng=lng,
                     stages=[st[i].stages for i in range(nwin)], sweeps=[st[i].sweeps for i in range(nwin)],
+                    converged=[bool(st[i].converged) for i in range(nwin)], spins=spins, E=E)
+
+    def muca_windows_run(self, L, lo, hi, walkers, seed, rec_sweeps, max_iter, flat=0.8, eq_sweeps=2,
+                         max_pass=1000, progress=None, ws=None):
+        """The multicanonical recursion in windows (mc_muca_windows_run);
+        returns a dict like oracle.muca_windows_run."""
+        import numpy as np
+
+        lo_a = np.ascontiguousarray(lo, dtype=np.int32)
+        hi_a = np.ascontiguousarray(hi, dtype=np.int32)
+        cb = WL_PROGRESS_FN(progress) if progress is not None else WL_PROGRESS_FN()
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        a = MucaWinArgs(L, lo_a.size, lo_a.ctypes.data_as(i32p), hi_a.ctypes.data_as(i32p), walkers, eq_sweeps,
+                        rec_sweeps, max_iter, float(flat), max_pass, seed, cb, None)
+        nwin = lo_a.size
+        wmax = int((hi_a - lo_a).max()) + 1
+        W = nwin * walkers
+        if ws is None:
+            n = int(_lib.mc_muca_windows_workspace_bytes(ctypes.byref(a)))
+            if n == 0:
+                raise MCError(MC_E_RANGE, "invalid windows or walkers")
+            ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        spins = torch.empty((W, L * L), dtype=torch.int8, device=self.device)
+        E = torch.empty(W, dtype=torch.int64, device=self.device)
+        pieces = np.zeros((nwin, wmax))
+        lng = np.zeros(L * L // 2 + 1)
+        st = (MucaWinStats * nwin)()
+        dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        rc = _lib.mc_muca_windows_run(self._h, ctypes.byref(a), _ptr(spins), _ptr(E), dp(pieces), dp(lng), st,
+                                      _ptr(ws), ws.numel(), _stream(self.device))
+        if rc not in (MC_OK, MC_E_NOTCONV):
+            self._check(rc, "mc_muca_windows_run")
+        return dict(pieces=[pieces[i, :hi_a[i] - lo_a[i] + 1].copy() for i in range(nwin)], lng=lng,
+                    iterations=[st[i].iterations for i in range(nwin)],
                     converged=[bool(st[i].converged) for i in range(nwin)], spins=spins, E=E)
 
     def set_tile_plan(self, geom, H, K, threads):

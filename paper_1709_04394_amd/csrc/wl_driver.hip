@@ -1,7 +1,9 @@
 // wl_driver.hip -- host side of Wang-Landau sampling in energy windows (Sec.
 // "Wang-Landau update"): argument checks, the exponential factors (FP64, libm
 // exp), the stage loop (flatness of every walker of a window, averaging, ln f
-// halved), and the matching of the windows' pieces on their overlaps.
+// halved), and the matching of the windows' pieces on their overlaps; and the
+// multicanonical recursion in the same windows (Sec. "Multicanonical
+// simulations"), on the same sweeps with ln f = 0.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -314,6 +316,137 @@ int mc_wl_run(mc_ctx *ctx, const mc_wl_args *a, int8_t *spins, int64_t *E, doubl
     }
     wl_match(K, nwin, a->lo, a->hi, pieces, wmax, lng);
     return left ? fail(ctx, MC_E_NOTCONV, "windows still above lnf_final after %lld sweeps", (long long)sweep) : MC_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+size_t mc_muca_windows_workspace_bytes(const mc_muca_win_args *a)
+{
+    if (!a) return 0;
+    mc_wl_args w{};
+    w.nwin = a->nwin;
+    w.lo = a->lo;
+    w.hi = a->hi;
+    w.walkers = a->walkers;
+    return mc_wl_workspace_bytes(&w);
+}
+
+int mc_muca_windows_run(mc_ctx *ctx, const mc_muca_win_args *a, int8_t *spins, int64_t *E, double *pieces,
+                        double *lng, mc_muca_win_stats *stats, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx) return MC_E_INVAL;
+    if (!a) return fail(ctx, MC_E_INVAL, "args is NULL");
+    int wmax = 0;
+    int rc = check_windows(ctx, a->L, a->nwin, a->lo, a->hi, true, &wmax);
+    if (rc) return rc;
+    if ((rc = check_walkers(ctx, a->nwin, a->walkers))) return rc;
+    if (!spins || !E || !pieces || !lng || !stats) return fail(ctx, MC_E_INVAL, "an output is NULL");
+    if (a->eq_sweeps < 0 || a->rec_sweeps < 1 || a->max_iter < 0 || a->max_pass < 1)
+        return fail(ctx, MC_E_RANGE, "eq_sweeps, rec_sweeps, max_iter or max_pass out of range");
+    if (!(a->flat > 0.0) || a->flat > 1.0) return fail(ctx, MC_E_RANGE, "flat must be in (0, 1]");
+    const int L = a->L, nwin = a->nwin, M = a->walkers, W = nwin * M, K = L * L / 2;
+    const WlLayout lay = wl_layout(nwin, M, wmax);
+    if (!ws || ws_bytes < lay.total) return fail(ctx, MC_E_WORKSPACE, "workspace needs %zu bytes", lay.total);
+    if ((rc = mc_win_drive(ctx, L, nwin, a->lo, a->hi, M, a->seed, a->max_pass, spins, E, ws, ws_bytes, stream)))
+        return rc;
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    int64_t *G = (int64_t *)(w + lay.G);
+    uint32_t *H = (uint32_t *)(w + lay.H);
+    int32_t *flags = (int32_t *)(w + lay.flat);
+    const int64_t hwords = ((int64_t)W * wmax + 1) / 2;
+    if ((rc = device_check(ctx, launch_fill_i64(G, (int64_t)W * wmax, 0, s), "weight clear"))) return rc;
+    if ((rc = device_check(ctx, launch_fill_i64((int64_t *)H, hwords, 0, s), "count clear"))) return rc;
+    std::vector<uint8_t> active((size_t)nwin, 1);
+    std::vector<int64_t> zero((size_t)nwin, 0), Gh((size_t)W * wmax, 0), sumH((size_t)wmax);
+    std::vector<uint32_t> Hh((size_t)W * wmax);
+    std::vector<int> iters((size_t)nwin, 0);
+    std::vector<char> done((size_t)nwin, 0);
+    int64_t sweep = 0;
+    // the piece of window i from its pooled counts and weights
+    auto piece = [&](int i) {
+        const int n = a->hi[i] - a->lo[i] + 1;
+        for (int j = 0; j < wmax; ++j) {
+            double v = 0.0;
+            if (j < n && sumH[(size_t)j] > 0)
+                v = std::log((double)sumH[(size_t)j]) + (double)Gh[(size_t)i * M * wmax + j] / 4294967296.0;
+            pieces[(size_t)i * wmax + j] = v;
+        }
+    };
+    auto pool = [&](int i) {
+        const int n = a->hi[i] - a->lo[i] + 1;
+        for (int j = 0; j < n; ++j) {
+            int64_t t = 0;
+            for (int m = 0; m < M; ++m) t += Hh[((size_t)i * M + m) * wmax + j];
+            sumH[(size_t)j] = t;
+        }
+    };
+    for (int it = 0; it < a->max_iter; ++it) {
+        if (std::none_of(active.begin(), active.end(), [](uint8_t v) { return v != 0; })) break;
+        if ((rc = mc_wl_sweeps(ctx, L, nwin, a->lo, a->hi, M, zero.data(), active.data(), a->flat, a->seed,
+                               (uint64_t)sweep, a->eq_sweeps, spins, E, G, H, flags, ws, ws_bytes, stream)))
+            return rc;
+        sweep += a->eq_sweeps;
+        if ((rc = device_check(ctx, launch_fill_i64((int64_t *)H, hwords, 0, s), "count clear"))) return rc;
+        if ((rc = mc_wl_sweeps(ctx, L, nwin, a->lo, a->hi, M, zero.data(), active.data(), a->flat, a->seed,
+                               (uint64_t)sweep, a->rec_sweeps, spins, E, G, H, flags, ws, ws_bytes, stream)))
+            return rc;
+        sweep += a->rec_sweeps;
+        if ((rc = download(ctx, Hh.data(), H, Hh.size() * 4, s))) return rc;
+        bool changed = false;
+        for (int i = 0; i < nwin; ++i) {
+            if (!active[(size_t)i]) continue;
+            ++iters[(size_t)i];
+            const int lo = a->lo[i], n = a->hi[i] - lo + 1;
+            pool(i);
+            int64_t mn = -1, mx = 0;
+            for (int j = 0; j < n; ++j) {
+                if (lo + j == 1) continue;
+                mn = mn < 0 ? sumH[(size_t)j] : std::min(mn, sumH[(size_t)j]);
+                mx = std::max(mx, sumH[(size_t)j]);
+            }
+            if ((double)mn >= a->flat * (double)mx) {
+                piece(i);
+                done[(size_t)i] = 1;
+                active[(size_t)i] = 0;
+                continue;
+            }
+            // ln W <- ln W - ln H where H > 0, i.e. G += round(ln H 2^32);
+            // then the minimum over the levels with states to 0
+            int64_t *g = Gh.data() + (size_t)i * M * wmax;
+            for (int j = 0; j < n; ++j)
+                if (sumH[(size_t)j] > 0)
+                    g[j] += (int64_t)std::floor(std::log((double)sumH[(size_t)j]) * 4294967296.0 + 0.5);
+            int64_t gmin = INT64_MAX;
+            for (int j = 0; j < n; ++j)
+                if (lo + j != 1) gmin = std::min(gmin, g[j]);
+            for (int j = 0; j < n; ++j) g[j] -= gmin;
+            for (int m = 1; m < M; ++m) std::copy(g, g + wmax, g + (size_t)m * wmax);
+            changed = true;
+        }
+        if (changed && (rc = upload(ctx, G, Gh.data(), Gh.size() * 8, s))) return rc;
+        if (a->progress) {
+            int nd = 0;
+            for (int i = 0; i < nwin; ++i) nd += done[(size_t)i];
+            a->progress(a->progress_user, nd, it + 1, sweep);
+        }
+    }
+    bool left = false;
+    for (int i = 0; i < nwin; ++i) {
+        if (!done[(size_t)i]) {
+            // not flat: the last recursion's weights, -ln W = G 2^-32
+            const int n = a->hi[i] - a->lo[i] + 1;
+            for (int j = 0; j < wmax; ++j)
+                pieces[(size_t)i * wmax + j] = j < n ? (double)Gh[(size_t)i * M * wmax + j] / 4294967296.0 : 0.0;
+            left = true;
+        }
+        stats[i].iterations = iters[(size_t)i];
+        stats[i].converged = done[(size_t)i] ? 1 : 0;
+    }
+    wl_match(K, nwin, a->lo, a->hi, pieces, wmax, lng);
+    return left ? fail(ctx, MC_E_NOTCONV, "windows not flat after %d iterations", a->max_iter) : MC_OK;
 }
 
 }  // extern "C"

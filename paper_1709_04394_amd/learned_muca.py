@@ -212,8 +212,10 @@ def main(argv=None):
             max |ln g error| of every production checkpoint, after matching
             the normalisations by log-sum-exp over the window levels with
             states (the accuracy metric) and after the best constant; the
-            walker-sweeps at the first checkpoint within the target; sweeps
-            to flat per arm over the seeds"""
+            walker-sweeps at the first checkpoint within the target; the
+            same for the runs at one seed's weights added together, with
+            the flat phase's walker-sweeps; sweeps to flat per arm over the
+            seeds"""
     import argparse
     import glob
     import json
@@ -258,6 +260,37 @@ def main(argv=None):
                 row["production"][os.path.basename(f)[:-4]] = dict(
                     meta, errors_logsumexp=[e[0] for e in errs], errors_best_constant=[e[1] for e in errs],
                     walker_sweeps_to_target=(reach[0] * meta["walkers"]) if reach else None)
+            # the runs at one seed's weights, in walker-seed order, their
+            # histograms added: the error after each checkpoint of the
+            # accumulated production, and the walker-sweeps (flat phase, 4096
+            # walkers, plus production) at the first within the target
+            summed = {}
+            for sd in seeds:
+                files = sorted(glob.glob(os.path.join(a.dir, "prod_%s_%d_*.npy" % (arm, sd))),
+                               key=lambda f: json.load(open(f[:-4] + ".json"))["pseed"])
+                if not files:
+                    continue
+                lnW = np.load(os.path.join(a.dir, "lnW_%s_%d.npy" % (arm, sd)))
+                base = None
+                done_ws = 0
+                curve = []
+                for f in files:
+                    meta = json.load(open(f[:-4] + ".json"))
+                    Hs = np.load(f).astype(np.int64)
+                    for cp, H in zip(meta["checkpoints"], Hs):
+                        tot = H if base is None else base + H
+                        e = lng_errors(tot, lnW, ex)
+                        curve.append({"walker_sweeps": done_ws + cp * meta["walkers"], "error_logsumexp": e[0],
+                                      "error_best_constant": e[1]})
+                    base = Hs[-1] if base is None else base + Hs[-1]
+                    done_ws += meta["checkpoints"][-1] * meta["walkers"]
+                flat_ws = conv["runs"][str(sd)][arm]["sweeps_per_walker_incl_prep"] * WALKERS
+                hit = [c["walker_sweeps"] for c in curve if c["error_logsumexp"] <= a.target]
+                summed[str(sd)] = {"runs": [os.path.basename(f)[:-4] for f in files], "curve": curve,
+                                   "flat_walker_sweeps": flat_ws,
+                                   "production_walker_sweeps_to_target": hit[0] if hit else None,
+                                   "total_walker_sweeps_to_target": flat_ws + hit[0] if hit else None}
+            row["summed_production"] = summed
             out["arms"][arm] = row
         pl, le = out["arms"]["plain"]["mean"], out["arms"]["learned"]["mean"]
         out["mean_sweeps_to_flat_ratio_learned_over_plain"] = le / pl

@@ -385,3 +385,37 @@ def test_wang_landau_argument_checks():
             assert run(b) == mcs.MC_E_RANGE, (l2, h2)
     finally:
         mcs._lib.mc_ctx_destroy(h)
+
+
+def test_windowed_multicanonical_argument_checks():
+    import numpy as np
+
+    h = ctypes.c_void_p()
+    assert mcs._lib.mc_ctx_create(ctypes.byref(h), 0) == 0
+    try:
+        fake = ctypes.c_void_p(1)
+        lo = np.array([0, 14], dtype=np.int32)
+        hi = np.array([20, 32], dtype=np.int32)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+
+        def args(**kw):
+            d = dict(eq=2, rec=10, it=5, flat=0.8, mp=10, lo=lo, hi=hi, M=64)
+            d.update(kw)
+            return mcs.MucaWinArgs(8, d["lo"].size, d["lo"].ctypes.data_as(i32p), d["hi"].ctypes.data_as(i32p), d["M"],
+                                   d["eq"], d["rec"], d["it"], d["flat"], d["mp"], 1, mcs.WL_PROGRESS_FN(), None)
+
+        a = args()
+        n = mcs._lib.mc_muca_windows_workspace_bytes(ctypes.byref(a))
+        assert n > 0
+        st = (mcs.MucaWinStats * 2)()
+        pieces = np.zeros((2, 21))
+        lng = np.zeros(33)
+        dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        run = lambda b, ws=fake, nb=n: mcs._lib.mc_muca_windows_run(h, ctypes.byref(b), fake, fake, dp(pieces),
+                                                                     dp(lng), st, ws, nb, None)
+        for kw in (dict(rec=0), dict(eq=-1), dict(it=-1), dict(flat=0.0), dict(mp=0), dict(M=96)):
+            assert run(args(**kw)) == mcs.MC_E_RANGE, kw
+        assert run(args(), ws=None) == mcs.MC_E_WORKSPACE
+        assert run(args(lo=np.array([0, 22], dtype=np.int32))) == mcs.MC_E_RANGE   # no overlap
+    finally:
+        mcs._lib.mc_ctx_destroy(h)

@@ -145,3 +145,20 @@ def _bench_windows(L, nwin):
     hi = [l + width - 1 for l in lo]
     hi[-1] = K
     return lo, hi
+
+
+@pytest.mark.parametrize("L,lo,hi,rec,max_iter", [
+    (8, [0, 14], [20, 32], 200, 100),
+    (16, [0, 40, 90], [60, 110, 128], 300, 100),
+    (16, [0, 40, 90], [60, 110, 128], 50, 6),   # stops early: not flat
+])
+def test_windowed_multicanonical_equals_oracle(ctx, L, lo, hi, rec, max_iter):
+    M = 64
+    r = ctx.muca_windows_run(L, lo, hi, M, 7, rec, max_iter)
+    o = oracle.muca_windows_run(L, lo, hi, M, 7, rec, max_iter)
+    assert r["iterations"] == o["iterations"]
+    assert r["converged"] == o["converged"]
+    for a, b in zip(r["pieces"], o["pieces"]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(r["lng"], o["lng"])
+    assert np.array_equal(r["E"].cpu().numpy(), o["E"])
