@@ -86,7 +86,12 @@ MUTANTS = [
     ("muca: wrong table column", "int col = d < 0 ? d + 2 : d + 1;", "int col = d < 0 ? d + 2 : d;"),
     ("muca: rejected moves not counted", "if (record) hw[(e + 2 * N) / 4] += 1;",
      "if (record && e == e2) hw[(e + 2 * N) / 4] += 1;"),
-    ("muca: walkers share one stream", "(uint32_t)i, (uint32_t)w, sweep);", "(uint32_t)i, 0u, sweep);"),
+    ("muca: walkers share one stream",
+     "if (e2 <= 0) {\n                        uint32_t r = orc_draw_word(seed, ORC_TAG_MUCA, (uint32_t)i, (uint32_t)w, sweep);",
+     "if (e2 <= 0) {\n                        uint32_t r = orc_draw_word(seed, ORC_TAG_MUCA, (uint32_t)i, 0u, sweep);"),
+    ("wl: walkers share one stream",
+     "                            uint32_t r = orc_draw_word(seed, ORC_TAG_MUCA, (uint32_t)i, (uint32_t)w, sweep);",
+     "                            uint32_t r = orc_draw_word(seed, ORC_TAG_MUCA, (uint32_t)i, 0u, sweep);"),
     ("muca: stratified rounding", "int64_t b = (int64_t)65536 * (2 * (int64_t)W - 2 * (int64_t)w - 1);",
      "int64_t b = (int64_t)65536 * (2 * (int64_t)W - 2 * (int64_t)w + 1);"),
     ("muca: start threshold off by one", "(uint32_t)w, 0, 0) >= 256u - c ? -1 : 1;",
