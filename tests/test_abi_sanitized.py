@@ -18,7 +18,7 @@ CSRC = os.path.join(ROOT, "paper_1709_04394_amd", "csrc")
 OBJS = os.path.join(ROOT, "paper_1709_04394_amd", "_build")
 HIPCC = "/opt/rocm/bin/hipcc"
 CLANG = "/opt/rocm/llvm/bin/clang"
-HOST_UNITS = ["abi", "tuning", "tempering", "sweep_driver", "pa_driver", "muca_driver", "mlp_driver"]
+HOST_UNITS = ["abi", "tuning", "tempering", "sweep_driver", "pa_driver", "muca_driver", "mlp_driver", "wl_driver"]
 
 DRIVER = r"""
 #include <stdint.h>
@@ -108,6 +108,34 @@ int main(int argc, char **argv)
     CHECK(mc_pt_exchange(ctx, 3, tb, tE, tof, rat, 1, (uint64_t)1 << 55, tacc) == MC_E_RANGE);
     tof[0] = tof[1];
     CHECK(mc_pt_exchange(ctx, 3, tb, tE, tof, rat, 1, 0, tacc) == MC_E_INVAL);
+
+    /* windows (host-side checks only; no device work) */
+    int32_t wlo[2] = {0, 14}, whi[2] = {20, 32}, gap_lo[2] = {0, 22};
+    mc_wl_args wa;
+    memset(&wa, 0, sizeof wa);
+    wa.L = 8; wa.nwin = 2; wa.lo = wlo; wa.hi = whi; wa.walkers = 64; wa.check_sweeps = 1;
+    wa.flat = 0.8; wa.lnf_final = 1e-4; wa.max_sweeps = 10; wa.max_pass = 10; wa.seed = 1;
+    size_t wsb = mc_wl_workspace_bytes(&wa);
+    CHECK(wsb > 0);
+    double wp[2 * 21], wl[33];
+    mc_wl_window_stats wst[2];
+    CHECK(mc_wl_run(ctx, &wa, FAKE, FAKE, wp, wl, wst, FAKE, wsb - 1, NULL) == MC_E_WORKSPACE);
+    wa.lnf_final = 2.0;
+    CHECK(mc_wl_run(ctx, &wa, FAKE, FAKE, wp, wl, wst, FAKE, wsb, NULL) == MC_E_RANGE);
+    wa.lnf_final = 1e-4; wa.lo = gap_lo;
+    CHECK(mc_wl_run(ctx, &wa, FAKE, FAKE, wp, wl, wst, FAKE, wsb, NULL) == MC_E_RANGE);
+    CHECK(mc_win_drive(ctx, 8, 2, wlo, whi, 32, 1, 10, FAKE, FAKE, FAKE, wsb, NULL) == MC_E_RANGE);
+    int64_t winc[2] = {1, -1};
+    uint8_t wact[2] = {1, 1};
+    CHECK(mc_wl_sweeps(ctx, 8, 2, wlo, whi, 64, winc, wact, 0.8, 1, 0, 1, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, wsb,
+                       NULL) == MC_E_RANGE);
+    mc_muca_win_args ma;
+    memset(&ma, 0, sizeof ma);
+    ma.L = 8; ma.nwin = 2; ma.lo = wlo; ma.hi = whi; ma.walkers = 64; ma.eq_sweeps = 2; ma.rec_sweeps = 0;
+    ma.max_iter = 5; ma.flat = 0.8; ma.max_pass = 10; ma.seed = 1;
+    mc_muca_win_stats mst[2];
+    CHECK(mc_muca_windows_workspace_bytes(&ma) == wsb);
+    CHECK(mc_muca_windows_run(ctx, &ma, FAKE, FAKE, wp, wl, mst, FAKE, wsb, NULL) == MC_E_RANGE);
 
     /* launch-shape file: round trip, then malformed files */
     CHECK(mc_tuning_save(ctx, argv[1]) == MC_OK);
