@@ -191,7 +191,8 @@ int mc_sweep_noalloc(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t
  * (with the same stationary distribution; no detailed balance).  EM: device
  * int64 [nsweeps][count][2], (E, M) after each sweep, or NULL.  ws: device
  * scratch of mc_dcb_workspace_bytes(geom) bytes (one bit-packed copy of the
- * lattices, updated in place by the sweeps' launches).  args->rule must be
+ * lattices, updated in place by the sweeps' launches, and per-tile (E, M)
+ * shares).  args->rule must be
  * MC_METROPOLIS (MC_E_LAYOUT otherwise); MC_E_SHAPE for an unsupported L or
  * tile; MC_E_RANGE for hits outside 1..1000 or (sweep0 + nsweeps) hits >=
  * 2^55.  Stream-ordered.                                                    */
@@ -629,7 +630,9 @@ int mc_wl_sweeps(mc_ctx *ctx, int32_t L, int32_t nwin, const int32_t *lo, const 
  * walker), clears the counts and halves ln f; it stops once ln f <
  * lnf_final.  The run ends when every window has stopped or after
  * max_sweeps (windows still running then report their current average and
- * MC_E_NOTCONV, with every output written).  Outputs on the host: pieces
+ * MC_E_NOTCONV, with every output written).  MC_E_RANGE if a stage would run
+ * so long that a walker's visits of one level could exceed 2^32 - 1 (N times
+ * the stage's sweeps).  Outputs on the host: pieces
  * [nwin][wmax] (window i's ln g at [i][k - lo[i]], in units of 1), lng
  * [N/2 + 1] (the matched ln g: window i + 1 shifted by the mean difference to
  * window i, as matched, over their overlap levels with states; level k taken

@@ -150,8 +150,9 @@ int pa_group_for(const mc_ctx *ctx, int L);
 // tile of one coarse colour of the packed lattices in place
 size_t dcb_lds_bytes(int T);
 hipError_t launch_dcb_phase(uint32_t *packed, int L, int T, int count, int coarse, int hits, uint32_t replica0,
-                            uint64_t sweep, uint32_t seed_lo, uint32_t seed_hi, const SweepTables &tab, int64_t *EM,
+                            uint64_t sweep, uint32_t seed_lo, uint32_t seed_hi, const SweepTables &tab, int64_t *part,
                             hipStream_t s);
+hipError_t launch_dcb_em(const int64_t *part, int L, int T, int count, int64_t *EM, hipStream_t s);
 
 // +-J spin glasses multi-spin coded across 64 disorder realisations with one
 // random number per site shared by the coded copies (k_sg_msc.hip)

@@ -17,8 +17,10 @@
 //
 // Energy and magnetisation of a sweep: every bond lies inside one tile or
 // joins a tile of colour 0 to one of colour 1.  Colour-0 tiles are final
-// after their launch and add their internal bonds and spins; colour-1 tiles
-// add theirs plus all bonds across their edges (the other ends are final).
+// after their launch and record their internal bonds and spins; colour-1
+// tiles record theirs plus all bonds across their edges (the other ends are
+// final).  Each tile writes its share to a slot of its own, and a small
+// kernel adds a lattice's slots after the sweep.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -37,7 +39,7 @@ struct DcbArgs {
     uint64_t sweep;             // global sweep number; hit h draws as plain sweep sweep * hits + h
     uint32_t seed_lo, seed_hi;
     Thr t4, t8;                 // Metropolis thresholds dE = 4, 8
-    int64_t *EM;                // (E, M) of this sweep per lattice, or nullptr
+    int64_t *part;              // [count][tiles][2] (E, M) shares of the tiles, or nullptr
 };
 
 // Workgroup -> tile: tiles of one coarse colour, (L/T)^2 / 2 of them, row by
@@ -204,7 +206,7 @@ __global__ __launch_bounds__(256) void k_dcb(DcbArgs a)
     }
 
     // ---- energy and magnetisation of this tile's share
-    if (!a.EM) return;
+    if (!a.part) return;
     long long e_acc = 0, m_acc = 0;
     const bool edges = a.coarse == 1;
     for (int t = tid; t < tasks; t += nt) {
@@ -256,17 +258,48 @@ __global__ __launch_bounds__(256) void k_dcb(DcbArgs a)
     }
     __syncthreads();
     if (tid == 0) {
+        // one slot per tile (a plain store: thousands of workgroups adding
+        // into the same two words would queue behind each other)
         long long te = 0, tm = 0;
         for (int i = 0; i < nwaves; ++i) te += red[0][i], tm += red[1][i];
-        atomicAdd((unsigned long long *)&a.EM[2 * l], (unsigned long long)te);
-        atomicAdd((unsigned long long *)&a.EM[2 * l + 1], (unsigned long long)tm);
+        const int nt2 = a.L / a.T;
+        int64_t *slot = a.part + 2 * ((int64_t)l * nt2 * nt2 + (int64_t)ty * nt2 + tx);
+        slot[0] = te;
+        slot[1] = tm;
+    }
+}
+
+// (E, M) of a sweep per lattice: the sum of its tiles' shares (both coarse
+// colours), one workgroup per lattice.
+__global__ __launch_bounds__(256) void k_dcb_em(const int64_t *part, int tiles, int64_t *EM)
+{
+    __shared__ long long red[2][4];
+    const int l = blockIdx.x, tid = threadIdx.x;
+    const int64_t *p = part + 2 * (int64_t)l * tiles;
+    long long e = 0, m = 0;
+    for (int i = tid; i < tiles; i += blockDim.x) e += p[2 * i], m += p[2 * i + 1];
+    e = wave_sum(e);
+    m = wave_sum(m);
+    if ((tid & 63) == 0) red[0][tid >> 6] = e, red[1][tid >> 6] = m;
+    __syncthreads();
+    if (tid == 0) {
+        long long te = 0, tm = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) te += red[0][i], tm += red[1][i];
+        EM[2 * l] = te;
+        EM[2 * l + 1] = tm;
     }
 }
 
 size_t dcb_lds_bytes(int T) { return (size_t)(T + 2) * 2 * (size_t)(T / 64 + 2) * 4; }
 
+hipError_t launch_dcb_em(const int64_t *part, int L, int T, int count, int64_t *EM, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dcb_em, dim3((unsigned)count), dim3(256), 0, s, part, (L / T) * (L / T), EM);
+    return hipGetLastError();
+}
+
 hipError_t launch_dcb_phase(uint32_t *packed, int L, int T, int count, int coarse, int hits, uint32_t replica0,
-                            uint64_t sweep, uint32_t seed_lo, uint32_t seed_hi, const SweepTables &tab, int64_t *EM,
+                            uint64_t sweep, uint32_t seed_lo, uint32_t seed_hi, const SweepTables &tab, int64_t *part,
                             hipStream_t s)
 {
     DcbArgs a;
@@ -281,7 +314,7 @@ hipError_t launch_dcb_phase(uint32_t *packed, int L, int T, int count, int coars
     a.seed_hi = seed_hi;
     a.t4 = tab.met[1];
     a.t8 = tab.met[2];
-    a.EM = EM;
+    a.part = part;
     const int tiles = (L / T) * (L / T) / 2;
     // one thread per word of a colour (T^2 / 64 of them), at most 256
     const int threads = std::min(256, T * T / 64);

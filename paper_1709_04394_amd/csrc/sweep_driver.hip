@@ -410,7 +410,9 @@ size_t mc_dcb_workspace_bytes(const mc_geom *geom)
     if (geom->dims != 2 || geom->layout != MC_INT8 || geom->Lx != geom->Ly || geom->Lx % 64 ||
         geom->Lx > 16384)
         return 0;
-    return packed_bytes(to_geom(geom));
+    // the packed lattices, then (E, M) slots for the smallest tile's count
+    const int64_t slots = (int64_t)geom->count * (geom->Lx / 64) * (geom->Lx / 64) * 2 * 8;
+    return ((packed_bytes(to_geom(geom)) + 255) & ~(size_t)255) + (size_t)slots;
 }
 
 int mc_sweep_dcb(mc_ctx *ctx, const mc_geom *geom, void *spins, const mc_sweep_args *args, int32_t tile,
@@ -433,8 +435,9 @@ int mc_sweep_dcb(mc_ctx *ctx, const mc_geom *geom, void *spins, const mc_sweep_a
     if ((args->sweep0 + (uint64_t)args->nsweeps) * (uint64_t)hits >= (1ull << 55))
         return fail(ctx, MC_E_RANGE, "sweep numbers times hits must stay below 2^55");
     const Geom g = to_geom(geom);
-    const size_t need = packed_bytes(g);
+    const size_t need = mc_dcb_workspace_bytes(geom);
     if (!ws || ws_bytes < need) return fail(ctx, MC_E_WORKSPACE, "workspace needs %zu bytes", need);
+    int64_t *part = (int64_t *)((char *)ws + ((packed_bytes(g) + 255) & ~(size_t)255));
     if (args->nsweeps == 0) return MC_OK;
     if ((rc = set_device(ctx))) return rc;
     hipStream_t s = (hipStream_t)stream;
@@ -451,12 +454,13 @@ int mc_sweep_dcb(mc_ctx *ctx, const mc_geom *geom, void *spins, const mc_sweep_a
     // conversions between int8 and packed rows: band launches of no sweeps
     const TilePlan conv = default_tile_plan(g);
     const int H = std::min(conv.H, g.Ly);
-    hipError_t e = EM ? launch_fill_i64(EM, 2 * (int64_t)args->nsweeps * g.count, 0, s) : hipSuccess;
-    if (e == hipSuccess) e = launch_tile2d(c, spins, 0, ws, 1, 0, 0, H, conv.threads, nullptr, 0, 0, s);
-    for (int t = 0; t < args->nsweeps && e == hipSuccess; ++t)
+    hipError_t e = launch_tile2d(c, spins, 0, ws, 1, 0, 0, H, conv.threads, nullptr, 0, 0, s);
+    for (int t = 0; t < args->nsweeps && e == hipSuccess; ++t) {
         for (int P = 0; P < 2 && e == hipSuccess; ++P)
             e = launch_dcb_phase((uint32_t *)ws, L, tile, g.count, P, hits, c.replica0, args->sweep0 + (uint64_t)t,
-                                 c.seed_lo, c.seed_hi, c.tab, EM ? EM + 2 * (int64_t)t * g.count : nullptr, s);
+                                 c.seed_lo, c.seed_hi, c.tab, EM ? part : nullptr, s);
+        if (EM && e == hipSuccess) e = launch_dcb_em(part, L, tile, g.count, EM + 2 * (int64_t)t * g.count, s);
+    }
     if (e == hipSuccess) e = launch_tile2d(c, ws, 1, spins, 0, 0, 0, H, conv.threads, nullptr, 0, 0, s);
     return device_check(ctx, e, "mc_sweep_dcb");
 }

@@ -255,12 +255,18 @@ int mc_wl_run(mc_ctx *ctx, const mc_wl_args *a, int8_t *spins, int64_t *E, doubl
         return rc;
     std::vector<int> stage((size_t)nwin, 0);
     std::vector<uint8_t> active((size_t)nwin, 1), mask((size_t)nwin, 0);
-    std::vector<int64_t> inc((size_t)nwin), sweeps((size_t)nwin, 0);
+    std::vector<int64_t> inc((size_t)nwin), sweeps((size_t)nwin, 0), in_stage((size_t)nwin, 0);
     std::vector<int32_t> fl((size_t)W);
     int64_t sweep = 0;
     auto any_active = [&]() { return std::any_of(active.begin(), active.end(), [](uint8_t v) { return v != 0; }); };
     while (any_active() && sweep < a->max_sweeps) {
-        for (int i = 0; i < nwin; ++i) inc[(size_t)i] = (int64_t)((1ull << 32) >> stage[(size_t)i]);
+        for (int i = 0; i < nwin; ++i) {
+            inc[(size_t)i] = (int64_t)((1ull << 32) >> stage[(size_t)i]);
+            // a walker's visits of one level within a stage are 32-bit counts
+            if (active[(size_t)i] && (in_stage[(size_t)i] + a->check_sweeps) * (int64_t)L * L > 0xFFFFFFFFll)
+                return fail(ctx, MC_E_RANGE, "window %d: a stage of %lld sweeps would overflow the visit counts", i,
+                            (long long)in_stage[(size_t)i]);
+        }
         if ((rc = mc_wl_sweeps(ctx, L, nwin, a->lo, a->hi, M, inc.data(), active.data(), a->flat, a->seed,
                                (uint64_t)sweep, a->check_sweeps, spins, E, G, H, flags, ws, ws_bytes, stream)))
             return rc;
@@ -271,11 +277,13 @@ int mc_wl_run(mc_ctx *ctx, const mc_wl_args *a, int8_t *spins, int64_t *E, doubl
             mask[(size_t)i] = 0;
             if (!active[(size_t)i]) continue;
             sweeps[(size_t)i] += a->check_sweeps;
+            in_stage[(size_t)i] += a->check_sweeps;
             bool all = true;
             for (int m = 0; m < M && all; ++m) all = fl[(size_t)i * M + m] != 0;
             if (!all) continue;
             mask[(size_t)i] = 1;
             avg = true;
+            in_stage[(size_t)i] = 0;
             ++stage[(size_t)i];
             if (std::ldexp(1.0, -stage[(size_t)i]) < a->lnf_final) active[(size_t)i] = 0;
         }

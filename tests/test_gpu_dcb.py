@@ -28,7 +28,9 @@ def _run(ctx, L, T, k, beta, seed, nsw, count=2, replica0=3, sweep0=0, calls=1, 
     spins = mcs.lattice_tensor(g)
     ctx.init(g, spins, start, seed, replica0)
     ws = torch.empty(ctx.dcb_workspace_bytes(g), dtype=torch.uint8, device="cuda")
-    assert ws.numel() == count * L * L // 8
+    # one packed copy (256-byte aligned) and an (E, M) slot per tile of side 64
+    packed = (count * L * L // 8 + 255) // 256 * 256
+    assert ws.numel() == packed + count * (L // 64) ** 2 * 16
     per = nsw // calls
     EMs = []
     for c in range(calls):
