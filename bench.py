@@ -36,7 +36,8 @@ VALU_FILE = os.path.join(ROOT, "profiles", "k_tile2d_L4096x3_valu.txt")
 # integer VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD
 # every 4 cycles (16 lanes per cycle), at 2.4 GHz
 VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
-KERNEL_SRC = os.path.join(ROOT, "paper_1709_04394_amd", "csrc", "k_tile2d.hip")
+# the dominant kernel's source files, hashed together in this order
+KERNEL_SRC = [os.path.join(ROOT, "paper_1709_04394_amd", "csrc", f) for f in ("k_tile2d.hip", "em_slots.hpp")]
 MLP_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # bands of 16 rows, 4 sweeps per launch, 512 threads: the autotuner's usual
 # pick on this workload (it alternates with 3 sweeps per launch within 1 %)
@@ -93,7 +94,10 @@ def _kv_for_kernel(path, plan):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    src = h.hexdigest()
     if kv.get("kernel_source_sha256") != src or kv.get("tile_plan") != "%d,%d,%d" % tuple(plan):
         return None
     return kv

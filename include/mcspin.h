@@ -120,9 +120,12 @@ int mc_couplings(mc_ctx *ctx, const mc_geom *geom, int8_t *J, uint64_t seed, voi
 
 /* Bytes of scratch mc_sweep can use to run several sweeps per fused launch:
  * two bit-packed copies of the lattices (count * Lz * Ly * Lx / 8 bytes
- * each), between which the launches of one call ping-pong, and in 3D the
- * couplings packed once per call (3 * Lz * Ly * Lx / 8 bytes); only the first
- * launch reads and only the last writes the caller's int8 lattices.  Non-zero
+ * each), between which the launches of one call ping-pong; in 3D the
+ * couplings packed once per call (3 * Lz * Ly * Lx / 8 bytes); then two
+ * arrays of per-tile (E, M) sums of one launch, each rounded up to a multiple
+ * of 256 bytes: 8 * count * ceil(Ly / 4) * 16 bytes in 2D, 4 * count *
+ * ceil(Ly / 4) * ceil(Lz / 4) * 16 in 3D.  Only the first launch reads and
+ * only the last writes the caller's int8 lattices.  Non-zero
  * for int8 geometries with Lx a multiple of 64: 2D with Lx <= 16384, 3D with
  * Lx <= 4096 and Ly, Lz >= 4.  With a smaller or NULL workspace mc_sweep uses
  * kernels that need none (a whole small lattice per workgroup, or per-half-
@@ -169,8 +172,8 @@ int mc_sweep_betas(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *
  * one device (different streams or host threads) race and must not be made;
  * calls in one stream are fine.  Errors: those of mc_sweep; MC_E_RANGE,
  * before any device work, when the geometry's fused scratch is larger than
- * the array (e.g. more than four 4096^2 lattices, or a 2D lattice above
- * 2^26 sites); geometries that need no scratch run as mc_sweep does without
+ * the array (e.g. more than three 4096^2 lattices, or a 2D lattice of 2^26
+ * sites); geometries that need no scratch run as mc_sweep does without
  * a workspace.  Stream-ordered.                                            */
 size_t mc_static_scratch_bytes(void);
 int mc_sweep_noalloc(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *J, const mc_sweep_args *args,
@@ -254,9 +257,9 @@ int mc_sweep_path(mc_ctx *ctx, const mc_geom *geom, int32_t rule, int32_t has_co
  * fixes it for the geometry (dims, extents, count) on this context;
  * mc_get_tile_plan reports the shape in use (the tuned or set one, else a
  * default).  Host-only calls.  A plan needs H >= 1, K >= 1 and threads a
- * multiple of 64 in 64..1024; in 2D K <= 8, the Lx/64 words of a row either
+ * multiple of 64 in 64..1024; in 2D H >= 4, K <= 8, the Lx/64 words of a row either
  * at most threads or a multiple of it, and (H + 4K) rows of 2 Lx/64 words
- * in at most 64 KB of LDS; in 3D K <= 4, Lx/64 <= threads, H <= min(Ly, Lz)
+ * in at most 64 KB of LDS; in 3D H >= 4, K <= 4, Lx/64 <= threads, H <= min(Ly, Lz)
  * and the tile with its couplings in at most 96 KB.  MC_E_RANGE otherwise,
  * the geometry's own errors as for mc_sweep.                               */
 int mc_set_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t H, int32_t K, int32_t threads);

@@ -11,6 +11,7 @@
 
 #include "../../include/mcspin.h"
 #include "common.hpp"
+#include "em_slots.hpp"
 
 namespace mcs {
 
@@ -110,17 +111,27 @@ size_t tile2d_lds_bytes(int Lx, int H, int K);
 // One fused launch of k sweeps (k = 0: conversion only).  src / dst are int8
 // lattices or, with in_packed / out_packed, the packed rows of the LDS layout
 // (per lattice Ly rows of 2 Lx/64 words, even-x array first); src != dst.
+// With em.slots set, a launch of k >= 1 sweeps stores every band's (E, M)
+// after each sweep in slots [k][count][tiles][2]; with em.red_in set, its
+// first workgroups add up the red_K sweeps of band sums of the previous launch
+// (same band height) into EM [red_sweep0 + j][count][2] (em_slots.hpp).
 hipError_t launch_tile2d(const SweepCall &c, const void *src, int in_packed, void *dst, int out_packed,
-                         uint64_t sweep0, int k, int H, int threads, int64_t *EM, int64_t em_stride, int64_t em_sweep0,
-                         hipStream_t s);
+                         uint64_t sweep0, int k, int H, int threads, const EmSlots &em, hipStream_t s);
+// Adds up K sweeps of per-tile sums (slots as above, tiles per lattice) into
+// EM [sweep0 + j][count][2].
+hipError_t launch_em_slots(const int64_t *slots, int tiles, int count, int K, int64_t *EM, int64_t em_stride,
+                           int64_t sweep0, hipStream_t s);
+size_t tile2d_slot_bytes(const Geom &g);
 TilePlan default_tile_plan(const Geom &g);
 
 // fused 3D kernel (k_tile3d.hip)
 bool tile3d_supported(const SweepCall &c, int layout);
 size_t tile3d_lds_bytes(int Lx, int H, int K, bool hasJ);
+// E, M as for the 2D kernel, one slot per H x H tile.
 hipError_t launch_tile3d(const SweepCall &c, const void *src, int in_packed, void *dst, int out_packed,
-                         const uint32_t *Jp, uint64_t sweep0, int k, int H, int threads, int64_t *EM,
-                         int64_t em_stride, int64_t em_sweep0, hipStream_t s);
+                         const uint32_t *Jp, uint64_t sweep0, int k, int H, int threads, const EmSlots &em,
+                         hipStream_t s);
+size_t tile3d_slot_bytes(const Geom &g);
 hipError_t launch_pack_couplings(const Geom &g, const int8_t *J, uint32_t *Jp, hipStream_t s);
 
 // int8 lattices with 32-site rows, bit-packed whole in one workgroup's LDS

@@ -30,9 +30,12 @@
 //    every bond has exactly one odd end, and when the odd sites of a row are
 //    updated its even sites are already final, so the band's own rows give E
 //    from the odd sites' four bonds and M from both parity words, with no
-//    extra pass; one int64 atomic per band and sweep.
+//    extra pass.  Each band stores its (E, M) share of every sweep in a slot
+//    of its own; the first workgroups of the next launch add them up
+//    (em_slots.hpp).
 //  * Several lattices (each with its own inverse temperature) can share one
 //    launch, which gives taller bands and so less redone halo.
+#include "em_slots.hpp"
 #include "internal.hpp"
 
 namespace mcs {
@@ -54,9 +57,7 @@ struct Tile2DArgs {
     int per_lattice;                // thresholds indexed by lattice (else entry 0)
     Thr t4[kMaxTableLattices];      // dE = 4
     Thr t8[kMaxTableLattices];      // dE = 8
-    int64_t *EM;                    // [sweep][count][2] of this call, or nullptr
-    int64_t em_stride;              // 2 * count
-    int64_t em_sweep0;              // index of this launch's first sweep within EM
+    EmSlots em;                     // band sums of this launch and the previous one
 };
 
 // Draw the low 24 bits of every tied site of one word (bits of p8 | p4) and
@@ -80,6 +81,7 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
 {
     extern __shared__ uint32_t lds[];
     __shared__ int red[2][16];
+    __shared__ long long red64[2][16];
     __shared__ uint32_t q_ws[kTieQueue], q_blk[kTieQueue], q_p8[kTieQueue], q_p4[kTieQueue];
     __shared__ uint32_t q_cnt[16];  // items queued by each wave in this half-sweep
     const int l = blockIdx.y;
@@ -120,6 +122,9 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
     const int wave = tid >> 6, nwaves = nt >> 6;
     const uint32_t wq_cap = (uint32_t)(kTieQueue / nwaves), wq_base = (uint32_t)wave * wq_cap;
     uint32_t wq_n = 0;
+    const int ntile = gridDim.x, nlat = gridDim.y;
+    long long pre_e, pre_m;
+    em_prefetch(a.em, blockIdx.x, ntile, l, nlat, tid, pre_e, pre_m);
 
     // ---- load rows y0-R .. y0+Hh+R-1
     if (a.in_packed) {
@@ -158,6 +163,7 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
         }
     }
     __syncthreads();
+    em_reduce(a.em, blockIdx.x, ntile, l, nlat, tid, nt, pre_e, pre_m, red64);
 
     for (int s = 0; s < K; ++s) {
         const uint64_t sweep = a.sweep0 + (uint64_t)s;
@@ -275,9 +281,7 @@ __global__ __launch_bounds__(1024) void k_tile2d(Tile2DArgs a)
                 te += red[0][i];
                 tm += red[1][i];
             }
-            int64_t *em = a.EM + (a.em_sweep0 + s) * a.em_stride + 2 * l;
-            atomicAdd((unsigned long long *)&em[0], (unsigned long long)te);
-            atomicAdd((unsigned long long *)&em[1], (unsigned long long)tm);
+            *em_slot(a.em.slots, s, l, nlat, blockIdx.x, ntile) = make_longlong2(te, tm);
         }
     }
 
@@ -332,17 +336,17 @@ static hipError_t launch_k(const Tile2DArgs &a, int count, int threads, hipStrea
     // allow the largest dynamic LDS a plan may ask for (64 KB) next to the
     // static tie queue, once per device and kernel instance
     static LdsLimit lim[2];
-    const void *f = a.EM ? (const void *)k_tile2d<K, true> : (const void *)k_tile2d<K, false>;
-    const hipError_t e = lim[a.EM ? 1 : 0].ensure(f, 65536);
+    const bool measure = a.em.slots != nullptr;
+    const void *f = measure ? (const void *)k_tile2d<K, true> : (const void *)k_tile2d<K, false>;
+    const hipError_t e = lim[measure ? 1 : 0].ensure(f, 65536);
     if (e != hipSuccess) return e;
-    if (a.EM) hipLaunchKernelGGL((k_tile2d<K, true>), grid, dim3(threads), lds, s, a);
+    if (measure) hipLaunchKernelGGL((k_tile2d<K, true>), grid, dim3(threads), lds, s, a);
     else hipLaunchKernelGGL((k_tile2d<K, false>), grid, dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_tile2d(const SweepCall &c, const void *src, int in_packed, void *dst, int out_packed,
-                         uint64_t sweep0, int k, int H, int threads, int64_t *EM, int64_t em_stride, int64_t em_sweep0,
-                         hipStream_t s)
+                         uint64_t sweep0, int k, int H, int threads, const EmSlots &em, hipStream_t s)
 {
     Tile2DArgs a;
     a.src = src;
@@ -363,9 +367,9 @@ hipError_t launch_tile2d(const SweepCall &c, const void *src, int in_packed, voi
         a.t4[i] = t.met[1];
         a.t8[i] = t.met[2];
     }
-    a.EM = k > 0 ? EM : nullptr;
-    a.em_stride = em_stride;
-    a.em_sweep0 = em_sweep0;
+    a.em = em;
+    if (k == 0) a.em.slots = nullptr;
+    if (!em.red_in) a.em.red_K = 0;
     switch (k) {
     case 0: return launch_k<0>(a, c.g.count, threads, s);
     case 1: return launch_k<1>(a, c.g.count, threads, s);
@@ -378,6 +382,54 @@ hipError_t launch_tile2d(const SweepCall &c, const void *src, int in_packed, voi
     case 8: return launch_k<8>(a, c.g.count, threads, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+// Adds up the workgroup sums of the last launch of a call: workgroup (j, l)
+// writes EM of sweep j of that launch for lattice l.
+__global__ __launch_bounds__(256) void k_em_slots(const int64_t *slots, int tiles, int64_t *EM, int64_t em_stride,
+                                                  int64_t sweep0)
+{
+    __shared__ long long part[2][4];
+    const int j = blockIdx.x, l = blockIdx.y, count = gridDim.y, tid = threadIdx.x;
+    const longlong2 *src = em_slot((int64_t *)slots, j, l, count, 0, tiles);
+    long long se = 0, sm = 0;
+    for (int t = tid; t < tiles; t += 256) {
+        const longlong2 v = src[t];
+        se += v.x;
+        sm += v.y;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        se += __shfl_xor(se, off, 64);
+        sm += __shfl_xor(sm, off, 64);
+    }
+    if ((tid & 63) == 0) {
+        part[0][tid >> 6] = se;
+        part[1][tid >> 6] = sm;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int64_t *em = EM + (sweep0 + j) * em_stride + 2 * l;
+        em[0] = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+        em[1] = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+    }
+}
+
+hipError_t launch_em_slots(const int64_t *slots, int tiles, int count, int K, int64_t *EM, int64_t em_stride,
+                           int64_t sweep0, hipStream_t s)
+{
+    if (K <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_em_slots, dim3((unsigned)K, (unsigned)count), dim3(256), 0, s, slots, tiles, EM, em_stride,
+                       sweep0);
+    return hipGetLastError();
+}
+
+// Per-band (E, M) slots of one launch: K <= 8 sweeps x count lattices x
+// ceil(Ly / 4) bands (a plan's band height is at least 4) x 16 bytes.
+size_t tile2d_slot_bytes(const Geom &g)
+{
+    const size_t b = (size_t)8 * (size_t)g.count * (size_t)((g.Ly + 3) / 4) * 16;
+    return (b + 255) / 256 * 256;
 }
 
 }  // namespace mcs

@@ -19,7 +19,8 @@
 //    threshold bit of every site comes from a multiplexer over the class bits,
 //    and r32 < T is one bit-serial comparison.  Ties (top byte equal) are
 //    queued per word and settled after the half-sweep.
-//  * Per-sweep E and M are summed from the odd half-sweep, as in 2D.
+//  * Per-sweep E and M are summed from the odd half-sweep, as in 2D, and
+//    stored per tile in slots that the next launch adds up (em_slots.hpp).
 //  * Between the launches of one call the lattice stays packed in global
 //    scratch.
 #include "internal.hpp"
@@ -43,8 +44,7 @@ struct Tile3DArgs {
     // (a <= 2); heat-bath: class d, T of h = 6 - 2d
     uint32_t top[kMaxTableLattices][8];
     uint32_t low[kMaxTableLattices][8];
-    int64_t *EM;
-    int64_t em_stride, em_sweep0;
+    EmSlots em;  // tile sums of this launch and the previous one
 };
 
 // floor(t / n) and t mod n for small non-negative t (below 2^20) through a
@@ -67,6 +67,7 @@ __global__ __launch_bounds__(1024) void k_tile3d(Tile3DArgs a)
 {
     extern __shared__ uint32_t lds[];
     __shared__ int red[2][16];
+    __shared__ long long red64[2][16];
     __shared__ uint32_t q_ws[kTieQ3], q_blk[kTieQ3], q_p[kTieQ3], q_c0[kTieQ3], q_c1[kTieQ3], q_c2[kTieQ3];
     __shared__ uint32_t q_cnt[16];
     __shared__ uint32_t tlow[8];
@@ -112,6 +113,9 @@ __global__ __launch_bounds__(1024) void k_tile3d(Tile3DArgs a)
     const uint32_t wq_cap = (uint32_t)(kTieQ3 / nwaves), wq_base = (uint32_t)wave * wq_cap;
     uint32_t wq_n = 0;
     const int64_t plane_rows = (int64_t)a.Ly * a.Lz;
+    const int ntile = gridDim.x, nlat = gridDim.y;
+    long long pre_e, pre_m;
+    em_prefetch(a.em, blockIdx.x, ntile, l, nlat, tid, pre_e, pre_m);
 
     // ---- load rows (z0-R .. z1+R-1) x (y0-R .. y1+R-1), row id = rz Ry + ry
     const float invRy = 1.0f / (float)Ry;
@@ -154,6 +158,7 @@ __global__ __launch_bounds__(1024) void k_tile3d(Tile3DArgs a)
         }
     }
     __syncthreads();
+    em_reduce(a.em, blockIdx.x, ntile, l, nlat, tid, nt, pre_e, pre_m, red64);
 
     for (int s = 0; s < K; ++s) {
         const uint64_t sweep = a.sweep0 + (uint64_t)s;
@@ -346,9 +351,7 @@ __global__ __launch_bounds__(1024) void k_tile3d(Tile3DArgs a)
                 te += red[0][i];
                 tm += red[1][i];
             }
-            int64_t *em = a.EM + (a.em_sweep0 + s) * a.em_stride + 2 * l;
-            atomicAdd((unsigned long long *)&em[0], (unsigned long long)te);
-            atomicAdd((unsigned long long *)&em[1], (unsigned long long)tm);
+            *em_slot(a.em.slots, s, l, nlat, blockIdx.x, ntile) = make_longlong2(te, tm);
         }
     }
 
@@ -425,11 +428,12 @@ static hipError_t launch3(const Tile3DArgs &a, int H, int count, int threads, hi
     dim3 grid((unsigned)(a.nty * a.ntz), (unsigned)count);
     static LdsLimit lim[2];
     {
-        const void *f = a.EM ? (const void *)k_tile3d<K, true, HB, HASJ> : (const void *)k_tile3d<K, false, HB, HASJ>;
-        const hipError_t e = lim[a.EM ? 1 : 0].ensure(f, 98304);
+        const void *f =
+            a.em.slots ? (const void *)k_tile3d<K, true, HB, HASJ> : (const void *)k_tile3d<K, false, HB, HASJ>;
+        const hipError_t e = lim[a.em.slots ? 1 : 0].ensure(f, 98304);
         if (e != hipSuccess) return e;
     }
-    if (a.EM) hipLaunchKernelGGL((k_tile3d<K, true, HB, HASJ>), grid, dim3(threads), lds, s, a);
+    if (a.em.slots) hipLaunchKernelGGL((k_tile3d<K, true, HB, HASJ>), grid, dim3(threads), lds, s, a);
     else hipLaunchKernelGGL((k_tile3d<K, false, HB, HASJ>), grid, dim3(threads), lds, s, a);
     return hipGetLastError();
 }
@@ -463,8 +467,8 @@ static void class_thresholds(const SweepTables &t, int rule, uint32_t *top, uint
 }
 
 hipError_t launch_tile3d(const SweepCall &c, const void *src, int in_packed, void *dst, int out_packed,
-                         const uint32_t *Jp, uint64_t sweep0, int k, int H, int threads, int64_t *EM,
-                         int64_t em_stride, int64_t em_sweep0, hipStream_t s)
+                         const uint32_t *Jp, uint64_t sweep0, int k, int H, int threads, const EmSlots &em,
+                         hipStream_t s)
 {
     Tile3DArgs a;
     a.src = src;
@@ -487,14 +491,22 @@ hipError_t launch_tile3d(const SweepCall &c, const void *src, int in_packed, voi
         const SweepTables &t = (c.per_lattice && i < c.g.count) ? c.tabs[i] : c.tab;
         class_thresholds(t, c.rule, a.top[i], a.low[i]);
     }
-    a.EM = k > 0 ? EM : nullptr;
-    a.em_stride = em_stride;
-    a.em_sweep0 = em_sweep0;
+    a.em = em;
+    if (k == 0) a.em.slots = nullptr;
+    if (!em.red_in) a.em.red_K = 0;
     const bool hb = c.rule == 1, hj = Jp != nullptr;
     if (hb && hj) return launch3k<true, true>(a, k, H, c.g.count, threads, s);
     if (hb) return launch3k<true, false>(a, k, H, c.g.count, threads, s);
     if (hj) return launch3k<false, true>(a, k, H, c.g.count, threads, s);
     return launch3k<false, false>(a, k, H, c.g.count, threads, s);
+}
+
+// Per-tile (E, M) slots of one launch: K <= 4 sweeps x count lattices x
+// ceil(Ly / 4) ceil(Lz / 4) tiles (a plan's tile side is at least 4) x 16 bytes.
+size_t tile3d_slot_bytes(const Geom &g)
+{
+    const size_t b = (size_t)4 * (size_t)g.count * (size_t)((g.Ly + 3) / 4) * (size_t)((g.Lz + 3) / 4) * 16;
+    return (b + 255) / 256 * 256;
 }
 
 hipError_t launch_pack_couplings(const Geom &g, const int8_t *J, uint32_t *Jp, hipStream_t s)

@@ -23,16 +23,17 @@ static bool fused3d_geom(const Geom &g, int layout)
     return layout == MC_INT8 && g.dims == 3 && g.Lx % 64 == 0 && g.Lx <= 4096 && g.Ly >= 4 && g.Lz >= 4;
 }
 
-// Two packed copies (ping-pong between the launches of one call); in 3D also
-// the couplings in packed form (three directions), whether or not a call has
+// Two packed copies (ping-pong between the launches of one call), two
+// arrays of per-tile (E, M) sums (ping-pong likewise) and, in 3D, the
+// couplings in packed form (three directions), whether or not a call has
 // couplings.
 size_t fused_workspace_bytes(const Geom &g, int layout)
 {
-    if (fused2d_geom(g, layout)) return 2 * packed_bytes(g);
+    if (fused2d_geom(g, layout)) return 2 * packed_bytes(g) + 2 * tile2d_slot_bytes(g);
     if (fused3d_geom(g, layout)) {
         Geom one = g;
         one.count = 1;
-        return 2 * packed_bytes(g) + 3 * packed_bytes(one);
+        return 2 * packed_bytes(g) + 3 * packed_bytes(one) + 2 * tile3d_slot_bytes(g);
     }
     return 0;
 }
@@ -78,9 +79,9 @@ static bool plan_ok(const Geom &g, const TilePlan &p)
     const int Wd = g.Lx / 64;
     if (p.H < 1 || p.K < 1 || p.threads < 64 || p.threads > 1024 || p.threads % 64 != 0) return false;
     if (g.dims == 3)
-        return p.K <= 4 && Wd <= p.threads && p.H <= std::min(g.Ly, g.Lz) &&
+        return p.H >= 4 && p.K <= 4 && Wd <= p.threads && p.H <= std::min(g.Ly, g.Lz) &&
                tile3d_lds_bytes(g.Lx, p.H, p.K, true) <= 98304;
-    return p.K <= 8 && (Wd <= p.threads || Wd % p.threads == 0) &&
+    return p.H >= 4 && p.K <= 8 && (Wd <= p.threads || Wd % p.threads == 0) &&
            tile2d_lds_bytes(g.Lx, std::min(p.H, g.Ly), p.K) <= 65536;
 }
 
@@ -110,34 +111,60 @@ static std::vector<int> split_launches(int n, int K)
 
 // Launch i reads the caller's int8 lattices (i = 0) or packed copy (i - 1) & 1
 // of the workspace, and writes packed copy i & 1 or, for the last launch, the
-// caller's lattices.
+// caller's lattices.  With EM, launch i also stores its per-tile sums in slot
+// array i & 1 and adds up those of launch i - 1 into EM; a small kernel adds
+// up the last launch's.
 static int run_fused(mc_ctx *ctx, const SweepCall &c, const TilePlan &p, int8_t *spins, char *ws, uint64_t sweep0,
                      int nsweeps, int64_t *EM, int64_t em_stride, hipStream_t s)
 {
     hipError_t e = hipSuccess;
-    if (EM) e = launch_fill_i64(EM, (int64_t)nsweeps * em_stride, 0, s);
+    const bool three = c.g.dims == 3;
     const std::vector<int> sizes = split_launches(nsweeps, p.K);
     char *pk[2] = {ws, ws + packed_bytes(c.g)};
-    const bool three = c.g.dims == 3;
+    char *after = ws + 2 * packed_bytes(c.g);
     uint32_t *Jp = nullptr;
-    if (three && c.J && e == hipSuccess) {
-        Jp = (uint32_t *)(ws + 2 * packed_bytes(c.g));
-        e = launch_pack_couplings(c.g, c.J, Jp, s);
+    if (three) {
+        Geom one = c.g;
+        one.count = 1;
+        if (c.J) {
+            Jp = (uint32_t *)after;
+            e = launch_pack_couplings(c.g, c.J, Jp, s);
+        }
+        after += 3 * packed_bytes(one);
     }
+    const size_t slot_bytes = three ? tile3d_slot_bytes(c.g) : tile2d_slot_bytes(c.g);
+    int64_t *slot[2] = {(int64_t *)after, (int64_t *)(after + slot_bytes)};
+    int tiles;
+    if (three) {
+        tiles = ((c.g.Ly + p.H - 1) / p.H) * ((c.g.Lz + p.H - 1) / p.H);
+    } else {
+        const int H = std::min(p.H, c.g.Ly);
+        tiles = (c.g.Ly + H - 1) / H;
+    }
+    EmSlots pend;  // tile sums not yet added up
+    pend.EM = EM;
+    pend.em_stride = em_stride;
     int done = 0;
     const size_t m = sizes.size();
     for (size_t i = 0; i < m && e == hipSuccess; ++i) {
         const bool first = i == 0, last = i + 1 == m;
         const void *src = first ? (const void *)spins : (const void *)pk[(i - 1) & 1];
         void *dst = last ? (void *)spins : (void *)pk[i & 1];
+        EmSlots em = pend;
+        em.slots = EM ? slot[i & 1] : nullptr;
         if (three)
             e = launch_tile3d(c, src, first ? 0 : 1, dst, last ? 0 : 1, Jp, sweep0 + (uint64_t)done, sizes[i], p.H,
-                              p.threads, EM, em_stride, done, s);
+                              p.threads, em, s);
         else
             e = launch_tile2d(c, src, first ? 0 : 1, dst, last ? 0 : 1, sweep0 + (uint64_t)done, sizes[i],
-                              std::min(p.H, c.g.Ly), p.threads, EM, em_stride, done, s);
+                              std::min(p.H, c.g.Ly), p.threads, em, s);
+        pend.red_in = EM && sizes[i] > 0 ? slot[i & 1] : nullptr;
+        pend.red_K = EM ? sizes[i] : 0;
+        pend.red_sweep0 = done;
         done += sizes[i];
     }
+    if (e == hipSuccess && pend.red_in)
+        e = launch_em_slots(pend.red_in, tiles, c.g.count, pend.red_K, EM, em_stride, pend.red_sweep0, s);
     return device_check(ctx, e, "mc_sweep fused launch");
 }
 
@@ -329,18 +356,18 @@ int mc_tune_sweep_rule(mc_ctx *ctx, const mc_geom *geom, int32_t rule, void *scr
         return fail(ctx, MC_E_DEVICE, "hipEventCreate failed");
     }
     auto launch = [&](const void *src, int inp, void *dst, int outp, uint64_t sweep0, int K, const TilePlan &p,
-                      int64_t *em) {
-        return three ? launch_tile3d(c, src, inp, dst, outp, nullptr, sweep0, K, p.H, p.threads, em, 2 * g.count, 0, s)
-                     : launch_tile2d(c, src, inp, dst, outp, sweep0, K, std::min(p.H, g.Ly), p.threads, em,
-                                     2 * g.count, 0, s);
+                      bool measure) {
+        // the tile sums go to the unused half of scratch_b and are not added
+        // up (the plans differ in the measuring launches only)
+        EmSlots te;
+        te.slots = measure ? (int64_t *)((char *)scratch_b + (size_t)g.count * (size_t)g.N / 2) : nullptr;
+        if (three) return launch_tile3d(c, src, inp, dst, outp, nullptr, sweep0, K, p.H, p.threads, te, s);
+        return launch_tile2d(c, src, inp, dst, outp, sweep0, K, std::min(p.H, g.Ly), p.threads, te, s);
     };
     // a hot lattice, packed into scratch_b
     TilePlan conv = default_tile_plan(g);
     hipError_t e = launch_init_int8(g, (int8_t *)scratch_a, 1, 1, 0, s);
-    if (e == hipSuccess) e = launch(scratch_a, 0, scratch_b, 1, 0, 0, conv, nullptr);
-    // per-sweep E, M of the timed launches: past the packed copy in scratch_a
-    // (count N / 8 bytes of packed rows; count N / 2 >= that + 16 K count)
-    int64_t *em = (int64_t *)((char *)scratch_a + (size_t)g.count * (size_t)g.N / 2);
+    if (e == hipSuccess) e = launch(scratch_a, 0, scratch_b, 1, 0, 0, conv, false);
     TilePlan best = default_tile_plan(g);
     float best_ms = 1e30f;
     std::vector<int> Hs, Ks, Ts;
@@ -362,19 +389,23 @@ int mc_tune_sweep_rule(mc_ctx *ctx, const mc_geom *geom, int32_t rule, void *scr
                 p.K = K;
                 p.threads = T;
                 if (!plan_ok(g, p) || e != hipSuccess) continue;
+                const int Hy = std::min(p.H, g.Ly);
+                const int64_t tiles =
+                    three ? (int64_t)((g.Ly + H - 1) / H) * ((g.Lz + H - 1) / H) : (int64_t)((g.Ly + Hy - 1) / Hy);
+                if ((size_t)K * (size_t)g.count * (size_t)tiles * 16 > (size_t)g.count * (size_t)g.N / 2)
+                    continue;  // tile sums larger than half of scratch_b
                 int n = std::max(sweeps, 2 * K);
                 n -= n % (2 * K);
                 // the steady state of a long measured call: packed -> packed
-                // launches between the two scratch buffers, per-sweep E, M into
-                // the unused tail of scratch_a; a warm-up launch, then the best
-                // of two timed runs
-                e = launch(scratch_b, 1, scratch_a, 1, 0, K, p, em);
+                // launches between the two scratch buffers, measuring E, M; a
+                // warm-up launch, then the best of two timed runs
+                e = launch(scratch_b, 1, scratch_a, 1, 0, K, p, true);
                 float ms = 1e30f;
                 for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
                     e = hipEventRecord(e0, s);
                     for (int i = 0; i < n / K && e == hipSuccess; ++i)
                         e = launch((i & 1) ? scratch_b : scratch_a, 1, (i & 1) ? scratch_a : scratch_b, 1,
-                                   (uint64_t)i * K, K, p, em);
+                                   (uint64_t)i * K, K, p, true);
                     if (e == hipSuccess) e = hipEventRecord(e1, s);
                     if (e == hipSuccess) e = hipEventSynchronize(e1);
                     float t = 0;
@@ -454,14 +485,14 @@ int mc_sweep_dcb(mc_ctx *ctx, const mc_geom *geom, void *spins, const mc_sweep_a
     // conversions between int8 and packed rows: band launches of no sweeps
     const TilePlan conv = default_tile_plan(g);
     const int H = std::min(conv.H, g.Ly);
-    hipError_t e = launch_tile2d(c, spins, 0, ws, 1, 0, 0, H, conv.threads, nullptr, 0, 0, s);
+    hipError_t e = launch_tile2d(c, spins, 0, ws, 1, 0, 0, H, conv.threads, EmSlots(), s);
     for (int t = 0; t < args->nsweeps && e == hipSuccess; ++t) {
         for (int P = 0; P < 2 && e == hipSuccess; ++P)
             e = launch_dcb_phase((uint32_t *)ws, L, tile, g.count, P, hits, c.replica0, args->sweep0 + (uint64_t)t,
                                  c.seed_lo, c.seed_hi, c.tab, EM ? part : nullptr, s);
         if (EM && e == hipSuccess) e = launch_dcb_em(part, L, tile, g.count, EM + 2 * (int64_t)t * g.count, s);
     }
-    if (e == hipSuccess) e = launch_tile2d(c, ws, 1, spins, 0, 0, 0, H, conv.threads, nullptr, 0, 0, s);
+    if (e == hipSuccess) e = launch_tile2d(c, ws, 1, spins, 0, 0, 0, H, conv.threads, EmSlots(), s);
     return device_check(ctx, e, "mc_sweep_dcb");
 }
 

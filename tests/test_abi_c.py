@@ -41,7 +41,7 @@ int main(void)
     if (strlen(mc_ctx_last_error(ctx)) == 0) return 14;
     sa.beta = -1.0;
     if (mc_sweep(ctx, &ok, (void *)0x1000, NULL, &sa, NULL, NULL, 0, NULL) != MC_E_RANGE) return 15;
-    if (mc_sweep_workspace_bytes(&ok) != 2 * 64 * 64 / 8) return 16;
+    if (mc_sweep_workspace_bytes(&ok) != 2 * 64 * 64 / 8 + 2 * 8 * 16 * 16) return 16;
     memset(&pa, 0, sizeof pa);
     pa.npop = 1;
     pa.L = L;

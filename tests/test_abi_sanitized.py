@@ -53,7 +53,7 @@ int main(int argc, char **argv)
     double betas[3] = {0.4, -0.1, 0.5};
     sa.beta = 0.4;
     CHECK(mc_sweep_betas(ctx, &g2, FAKE, NULL, &sa, betas, NULL, NULL, 0, NULL) == MC_E_RANGE);
-    CHECK(mc_sweep_workspace_bytes(&g2) == 2ull * 3 * 4096 * 4096 / 8);
+    CHECK(mc_sweep_workspace_bytes(&g2) == 2ull * 3 * 4096 * 4096 / 8 + 2ull * 8 * 3 * 1024 * 16);
 
     /* kernel family and launch shapes */
     int32_t path = 0;

@@ -29,7 +29,8 @@ def _gpu_run(ctx, shape, beta, seed, nsweeps, sweep0, count, replica0, plan, sta
     spins = mcs.lattice_tensor(g)
     ctx.init(g, spins, start, seed, replica0)
     ws = torch.empty(ctx.sweep_workspace_bytes(g), dtype=torch.uint8, device="cuda")
-    assert ws.numel() == 2 * count * g.N // 8  # two bit-packed copies
+    # two bit-packed copies and two arrays of per-band (E, M) sums
+    assert ws.numel() == 2 * count * g.N // 8 + 2 * (-(-8 * count * -(-shape[1] // 4) * 16 // 256) * 256)
     if plan is not None:
         ctx.set_tile_plan(g, *plan)
     EM = torch.empty((nsweeps, count, 2), dtype=torch.int64, device="cuda")
@@ -52,7 +53,8 @@ def _oracle_run(shape, beta, seed, nsweeps, sweep0, count, replica0, start=None)
 @pytest.mark.parametrize("shape,plan", [((64, 64), (4, 1, 64)), ((64, 64), (8, 2, 128)), ((64, 64), (16, 3, 256)),
                                         ((64, 64), (5, 4, 512)), ((64, 64), (64, 8, 1024)),
                                         ((128, 36), (7, 2, 192)), ((192, 20), (64, 3, 256)),
-                                        ((64, 4), (2, 1, 64)), ((64, 6), (4, 4, 128)), ((256, 132), None)])
+                                        ((64, 4), (4, 3, 64)), ((64, 6), (4, 4, 128)), ((256, 132), None),
+                                        ((64, 1100), (4, 2, 64))])
 @pytest.mark.parametrize("nsweeps", [1, 3, 8, 21])
 def test_fused_matches_oracle(ctx, shape, plan, nsweeps):
     beta, seed, sweep0, count, rep0 = 0.4406868, 29, (1 << 32) - 2, 2, 3
