@@ -163,7 +163,7 @@ int mc_sweep_betas(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *
  * tight serving loops, harnesses that forbid allocation): mc_sweep without a
  * workspace argument.  The scratch the fused kernels need (the size
  * mc_sweep_workspace_bytes reports) comes from a device array of the library
- * of mc_static_scratch_bytes() bytes (16 MiB), one per device, held until
+ * of mc_static_scratch_bytes() bytes (20 MiB), one per device, held until
  * the process ends; its address is looked up once per device on the first
  * call.  The call allocates nothing: no hipMalloc, hipFree or allocating
  * library routine.  Results are those of mc_sweep with a large enough
@@ -172,7 +172,7 @@ int mc_sweep_betas(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t *
  * one device (different streams or host threads) race and must not be made;
  * calls in one stream are fine.  Errors: those of mc_sweep; MC_E_RANGE,
  * before any device work, when the geometry's fused scratch is larger than
- * the array (e.g. more than three 4096^2 lattices, or a 2D lattice of 2^26
+ * the array (e.g. more than four 4096^2 lattices, or a 2D lattice of 2^27
  * sites); geometries that need no scratch run as mc_sweep does without
  * a workspace.  Stream-ordered.                                            */
 size_t mc_static_scratch_bytes(void);
@@ -193,9 +193,11 @@ int mc_sweep_noalloc(mc_ctx *ctx, const mc_geom *geom, void *spins, const int8_t
  * colour index, colour).  This is a different Markov chain from mc_sweep's
  * (with the same stationary distribution; no detailed balance).  EM: device
  * int64 [nsweeps][count][2], (E, M) after each sweep, or NULL.  ws: device
- * scratch of mc_dcb_workspace_bytes(geom) bytes (one bit-packed copy of the
- * lattices, updated in place by the sweeps' launches, and per-tile (E, M)
- * shares).  args->rule must be
+ * scratch of mc_dcb_workspace_bytes(geom) bytes: one bit-packed copy of the
+ * lattices (count * L * L / 8 bytes, rounded up to a multiple of 256),
+ * updated in place by the sweeps' launches, then two arrays of per-tile
+ * (E, M) shares used by alternate sweeps (count * (L / 64)^2 * 16 bytes
+ * each, rounded up likewise).  args->rule must be
  * MC_METROPOLIS (MC_E_LAYOUT otherwise); MC_E_SHAPE for an unsupported L or
  * tile; MC_E_RANGE for hits outside 1..1000 or (sweep0 + nsweeps) hits >=
  * 2^55.  Stream-ordered.                                                    */

@@ -19,7 +19,7 @@ namespace mcs {
 // (3D), sweeps per launch and threads per workgroup.  Any choice gives the
 // same results.
 // Size of the device array behind mc_sweep_noalloc (one copy per device).
-constexpr size_t kStaticScratchBytes = (size_t)16 << 20;
+constexpr size_t kStaticScratchBytes = (size_t)20 << 20;
 
 struct TilePlan {
     int H = 16;
@@ -160,10 +160,11 @@ int pa_group_for(const mc_ctx *ctx, int L);
 // double-checkerboard multi-hit sweeps (k_dcb.hip): one launch updates every
 // tile of one coarse colour of the packed lattices in place
 size_t dcb_lds_bytes(int T);
+// part: this sweep's (E, M) slots [count][(L/T)^2][2], or nullptr; prev: the
+// previous sweep's slots, added up by the first workgroup of each lattice
 hipError_t launch_dcb_phase(uint32_t *packed, int L, int T, int count, int coarse, int hits, uint32_t replica0,
                             uint64_t sweep, uint32_t seed_lo, uint32_t seed_hi, const SweepTables &tab, int64_t *part,
-                            hipStream_t s);
-hipError_t launch_dcb_em(const int64_t *part, int L, int T, int count, int64_t *EM, hipStream_t s);
+                            const EmSlots &prev, hipStream_t s);
 
 // +-J spin glasses multi-spin coded across 64 disorder realisations with one
 // random number per site shared by the coded copies (k_sg_msc.hip)

@@ -19,8 +19,10 @@
 // joins a tile of colour 0 to one of colour 1.  Colour-0 tiles are final
 // after their launch and record their internal bonds and spins; colour-1
 // tiles record theirs plus all bonds across their edges (the other ends are
-// final).  Each tile writes its share to a slot of its own, and a small
-// kernel adds a lattice's slots after the sweep.
+// final).  Each tile writes its share to a slot of its own; the first
+// workgroup of each lattice in the next sweep's colour-0 launch adds up the
+// previous sweep's slots while it loads its tile (em_slots.hpp), and a small
+// kernel adds up those of a call's last sweep.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -40,6 +42,7 @@ struct DcbArgs {
     uint32_t seed_lo, seed_hi;
     Thr t4, t8;                 // Metropolis thresholds dE = 4, 8
     int64_t *part;              // [count][tiles][2] (E, M) shares of the tiles, or nullptr
+    EmSlots prev;               // the previous sweep's slots (red_K = 1) to add up, or none
 };
 
 // Workgroup -> tile: tiles of one coarse colour, (L/T)^2 / 2 of them, row by
@@ -57,6 +60,7 @@ __global__ __launch_bounds__(256) void k_dcb(DcbArgs a)
     __shared__ uint32_t q_ws[kDcbTieQueue], q_blk[kDcbTieQueue], q_p8[kDcbTieQueue], q_p4[kDcbTieQueue];
     __shared__ uint32_t q_cnt[kDcbMaxWaves];
     __shared__ long long red[2][kDcbMaxWaves];
+    __shared__ long long red_prev[2][16];
     const int l = blockIdx.y;
     int tx, ty;
     dcb_tile(a, blockIdx.x, tx, ty);
@@ -86,6 +90,9 @@ __global__ __launch_bounds__(256) void k_dcb(DcbArgs a)
     };
     const TopMask m4 = top_mask(a.t4.top), m8 = top_mask(a.t8.top);
     const uint32_t wq_cap = (uint32_t)(kDcbTieQueue / nwaves), wq_base = (uint32_t)wave * wq_cap;
+    const int slots_per_lattice = (a.L / a.T) * (a.L / a.T);
+    long long pre_e, pre_m;
+    em_prefetch(a.prev, blockIdx.x, slots_per_lattice, l, gridDim.y, tid, pre_e, pre_m);
 
     // ---- load the tile and its halo (corner words are not needed), a batch
     // of words per thread in flight at once
@@ -108,6 +115,7 @@ __global__ __launch_bounds__(256) void k_dcb(DcbArgs a)
             if (i0 + j * nt < ld) lds[i0 + j * nt] = v[j];
     }
     __syncthreads();
+    em_reduce(a.prev, blockIdx.x, slots_per_lattice, l, gridDim.y, tid, nt, pre_e, pre_m, red_prev);
 
     const int tasks = a.T * Wt;  // words of one colour: one per (row, column)
     uint32_t wq_n = 0;
@@ -269,38 +277,11 @@ __global__ __launch_bounds__(256) void k_dcb(DcbArgs a)
     }
 }
 
-// (E, M) of a sweep per lattice: the sum of its tiles' shares (both coarse
-// colours), one workgroup per lattice.
-__global__ __launch_bounds__(256) void k_dcb_em(const int64_t *part, int tiles, int64_t *EM)
-{
-    __shared__ long long red[2][4];
-    const int l = blockIdx.x, tid = threadIdx.x;
-    const int64_t *p = part + 2 * (int64_t)l * tiles;
-    long long e = 0, m = 0;
-    for (int i = tid; i < tiles; i += blockDim.x) e += p[2 * i], m += p[2 * i + 1];
-    e = wave_sum(e);
-    m = wave_sum(m);
-    if ((tid & 63) == 0) red[0][tid >> 6] = e, red[1][tid >> 6] = m;
-    __syncthreads();
-    if (tid == 0) {
-        long long te = 0, tm = 0;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) te += red[0][i], tm += red[1][i];
-        EM[2 * l] = te;
-        EM[2 * l + 1] = tm;
-    }
-}
-
 size_t dcb_lds_bytes(int T) { return (size_t)(T + 2) * 2 * (size_t)(T / 64 + 2) * 4; }
-
-hipError_t launch_dcb_em(const int64_t *part, int L, int T, int count, int64_t *EM, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_dcb_em, dim3((unsigned)count), dim3(256), 0, s, part, (L / T) * (L / T), EM);
-    return hipGetLastError();
-}
 
 hipError_t launch_dcb_phase(uint32_t *packed, int L, int T, int count, int coarse, int hits, uint32_t replica0,
                             uint64_t sweep, uint32_t seed_lo, uint32_t seed_hi, const SweepTables &tab, int64_t *part,
-                            hipStream_t s)
+                            const EmSlots &prev, hipStream_t s)
 {
     DcbArgs a;
     a.lat = packed;
@@ -315,6 +296,8 @@ hipError_t launch_dcb_phase(uint32_t *packed, int L, int T, int count, int coars
     a.t4 = tab.met[1];
     a.t8 = tab.met[2];
     a.part = part;
+    a.prev = prev;
+    if (!prev.red_in) a.prev.red_K = 0;
     const int tiles = (L / T) * (L / T) / 2;
     // one thread per word of a colour (T^2 / 64 of them), at most 256
     const int threads = std::min(256, T * T / 64);

@@ -435,15 +435,21 @@ int mc_tune_sweep_rule(mc_ctx *ctx, const mc_geom *geom, int32_t rule, void *scr
 // tiles), and the last step unpacks them.
 extern "C" {
 
+// The packed lattices, then two arrays of (E, M) slots (consecutive sweeps
+// alternate) for the smallest tile's count, each rounded up to 256 bytes.
+static size_t dcb_slot_bytes(const mc_geom *geom)
+{
+    const size_t b = (size_t)geom->count * (size_t)(geom->Lx / 64) * (size_t)(geom->Lx / 64) * 2 * 8;
+    return (b + 255) & ~(size_t)255;
+}
+
 size_t mc_dcb_workspace_bytes(const mc_geom *geom)
 {
     if (!geom || check_geom(nullptr, geom, true) != MC_OK) return 0;
     if (geom->dims != 2 || geom->layout != MC_INT8 || geom->Lx != geom->Ly || geom->Lx % 64 ||
         geom->Lx > 16384)
         return 0;
-    // the packed lattices, then (E, M) slots for the smallest tile's count
-    const int64_t slots = (int64_t)geom->count * (geom->Lx / 64) * (geom->Lx / 64) * 2 * 8;
-    return ((packed_bytes(to_geom(geom)) + 255) & ~(size_t)255) + (size_t)slots;
+    return ((packed_bytes(to_geom(geom)) + 255) & ~(size_t)255) + 2 * dcb_slot_bytes(geom);
 }
 
 int mc_sweep_dcb(mc_ctx *ctx, const mc_geom *geom, void *spins, const mc_sweep_args *args, int32_t tile,
@@ -468,7 +474,8 @@ int mc_sweep_dcb(mc_ctx *ctx, const mc_geom *geom, void *spins, const mc_sweep_a
     const Geom g = to_geom(geom);
     const size_t need = mc_dcb_workspace_bytes(geom);
     if (!ws || ws_bytes < need) return fail(ctx, MC_E_WORKSPACE, "workspace needs %zu bytes", need);
-    int64_t *part = (int64_t *)((char *)ws + ((packed_bytes(g) + 255) & ~(size_t)255));
+    char *slots = (char *)ws + ((packed_bytes(g) + 255) & ~(size_t)255);
+    int64_t *part[2] = {(int64_t *)slots, (int64_t *)(slots + dcb_slot_bytes(geom))};
     if (args->nsweeps == 0) return MC_OK;
     if ((rc = set_device(ctx))) return rc;
     hipStream_t s = (hipStream_t)stream;
@@ -486,12 +493,25 @@ int mc_sweep_dcb(mc_ctx *ctx, const mc_geom *geom, void *spins, const mc_sweep_a
     const TilePlan conv = default_tile_plan(g);
     const int H = std::min(conv.H, g.Ly);
     hipError_t e = launch_tile2d(c, spins, 0, ws, 1, 0, 0, H, conv.threads, EmSlots(), s);
+    // sweep t stores its tiles' (E, M) in part[t & 1]; the colour-0 launch of
+    // sweep t + 1 adds them up into EM row t, a small kernel those of the last
+    const int tiles = (L / tile) * (L / tile);
     for (int t = 0; t < args->nsweeps && e == hipSuccess; ++t) {
+        EmSlots prev;
+        if (EM && t > 0) {
+            prev.red_in = part[(t - 1) & 1];
+            prev.red_K = 1;
+            prev.red_sweep0 = t - 1;
+            prev.EM = EM;
+            prev.em_stride = 2 * (int64_t)g.count;
+        }
         for (int P = 0; P < 2 && e == hipSuccess; ++P)
             e = launch_dcb_phase((uint32_t *)ws, L, tile, g.count, P, hits, c.replica0, args->sweep0 + (uint64_t)t,
-                                 c.seed_lo, c.seed_hi, c.tab, EM ? part : nullptr, s);
-        if (EM && e == hipSuccess) e = launch_dcb_em(part, L, tile, g.count, EM + 2 * (int64_t)t * g.count, s);
+                                 c.seed_lo, c.seed_hi, c.tab, EM ? part[t & 1] : nullptr, P == 0 ? prev : EmSlots(), s);
     }
+    if (EM && e == hipSuccess)
+        e = launch_em_slots(part[(args->nsweeps - 1) & 1], tiles, g.count, 1, EM, 2 * (int64_t)g.count,
+                            args->nsweeps - 1, s);
     if (e == hipSuccess) e = launch_tile2d(c, ws, 1, spins, 0, 0, 0, H, conv.threads, EmSlots(), s);
     return device_check(ctx, e, "mc_sweep_dcb");
 }

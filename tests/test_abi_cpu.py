@@ -290,9 +290,9 @@ def test_dcb_argument_checks():
             return mcs._lib.mc_sweep_dcb(h, ctypes.byref(g), fake, ctypes.byref(a), tile, hits, None, fake, wsb, None)
 
         g = mcs.make_geom(2, 512, count=2)
-        # the packed lattices (256-byte aligned) and an (E, M) slot per tile of
-        # the smallest tile side, 64
-        assert mcs._lib.mc_dcb_workspace_bytes(ctypes.byref(g)) == 2 * 512 * 512 // 8 + 2 * (512 // 64) ** 2 * 16
+        # the packed lattices (256-byte aligned) and two arrays of an (E, M)
+        # slot per tile of the smallest tile side, 64
+        assert mcs._lib.mc_dcb_workspace_bytes(ctypes.byref(g)) == 2 * 512 * 512 // 8 + 2 * 2 * (512 // 64) ** 2 * 16
         assert mcs._lib.mc_dcb_workspace_bytes(ctypes.byref(mcs.make_geom(2, (512, 256)))) == 0
         assert mcs._lib.mc_dcb_workspace_bytes(ctypes.byref(mcs.make_geom(3, 64))) == 0
         assert call(g, rule=mcs.HEATBATH) == mcs.MC_E_LAYOUT

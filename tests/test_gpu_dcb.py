@@ -28,9 +28,10 @@ def _run(ctx, L, T, k, beta, seed, nsw, count=2, replica0=3, sweep0=0, calls=1, 
     spins = mcs.lattice_tensor(g)
     ctx.init(g, spins, start, seed, replica0)
     ws = torch.empty(ctx.dcb_workspace_bytes(g), dtype=torch.uint8, device="cuda")
-    # one packed copy (256-byte aligned) and an (E, M) slot per tile of side 64
-    packed = (count * L * L // 8 + 255) // 256 * 256
-    assert ws.numel() == packed + count * (L // 64) ** 2 * 16
+    # one packed copy and two arrays of an (E, M) slot per tile of side 64,
+    # each 256-byte aligned
+    up = lambda b: (b + 255) // 256 * 256
+    assert ws.numel() == up(count * L * L // 8) + 2 * up(count * (L // 64) ** 2 * 16)
     per = nsw // calls
     EMs = []
     for c in range(calls):
@@ -60,6 +61,13 @@ def test_dcb_temperatures_and_cold_start(ctx, beta):
 
 def test_dcb_split_calls(ctx):
     _run(ctx, 256, 128, 4, 0.44, 63, 6, calls=3)
+    _run(ctx, 256, 64, 2, 0.44, 64, 3, calls=3)  # one sweep per call
+
+
+def test_dcb_many_tiles_per_lattice(ctx):
+    # 1024 tiles of 64 per lattice: the slots of a sweep outnumber the threads
+    # of the workgroup that adds them up
+    _run(ctx, 2048, 64, 1, 0.44068679350977147, 65, 3, count=1)
 
 
 def test_dcb_benchmark_lattice_prefix(ctx):

@@ -49,11 +49,12 @@ def ctx_h():
 
 
 def test_scratch_size_reported():
-    assert mcs._lib.mc_static_scratch_bytes() == 16 << 20
+    assert mcs._lib.mc_static_scratch_bytes() == 20 << 20
 
 
 def test_too_large_geometry_refused_before_device_work(ctx_h):
-    # five 4096^2 lattices need 2 * 5 * 4096^2 / 8 B = 20 MiB of packed rows
+    # five 4096^2 lattices need 2 * 5 * 4096^2 / 8 B = 20 MiB of packed rows and
+    # 2 * 640 KiB of (E, M) slots
     g = mcs.make_geom(2, 4096, count=5)
     a = _args(0.44, 1, 3)
     fake = ctypes.c_void_p(1)
@@ -72,7 +73,7 @@ def test_too_large_geometry_refused_before_device_work(ctx_h):
     # (dims, first shape, first count, second shape, second count, rule, beta)
     (2, (512, 260), 3, (256, 68), 2, mcs.METROPOLIS, 0.4406868),
     (3, (128, 20, 18), 2, (64, 12, 8), 1, mcs.HEATBATH, 0.2216546),
-    (2, (4096, 4096), 3, (1024, 1024), 1, mcs.METROPOLIS, 0.5),
+    (2, (4096, 4096), 4, (1024, 1024), 1, mcs.METROPOLIS, 0.5),
 ])
 def test_noalloc_equals_sweep_with_workspace(ctx_h, case):
     if not torch.cuda.is_available():
