@@ -23,7 +23,7 @@ def ctx():
     return mcs.Context(0)
 
 
-def _gpu_run(ctx, shape, beta, seed, nsweeps, sweep0, count, replica0, plan, start=None):
+def _gpu_run(ctx, shape, beta, seed, nsweeps, sweep0, count, replica0, plan, start=None, measure=True):
     start = mcs.HOT if start is None else start
     g = mcs.make_geom(2, shape, count=count)
     spins = mcs.lattice_tensor(g)
@@ -33,10 +33,10 @@ def _gpu_run(ctx, shape, beta, seed, nsweeps, sweep0, count, replica0, plan, sta
     assert ws.numel() == 2 * count * g.N // 8 + 2 * (-(-8 * count * -(-shape[1] // 4) * 16 // 256) * 256)
     if plan is not None:
         ctx.set_tile_plan(g, *plan)
-    EM = torch.empty((nsweeps, count, 2), dtype=torch.int64, device="cuda")
+    EM = torch.empty((nsweeps, count, 2), dtype=torch.int64, device="cuda") if measure else None
     ctx.sweep(g, spins, beta, seed, nsweeps, sweep0=sweep0, replica0=replica0, EM=EM, ws=ws)
     torch.cuda.synchronize()
-    return spins.cpu().numpy(), EM.cpu().numpy()
+    return spins.cpu().numpy(), EM.cpu().numpy() if measure else None
 
 
 def _oracle_run(shape, beta, seed, nsweeps, sweep0, count, replica0, start=None):
@@ -62,6 +62,16 @@ def test_fused_matches_oracle(ctx, shape, plan, nsweeps):
     os_, oem = _oracle_run(shape, beta, seed, nsweeps, sweep0, count, rep0)
     assert np.array_equal(gs, os_)
     assert np.array_equal(gem, oem)
+
+
+@pytest.mark.parametrize("nsweeps", [1, 9])
+def test_fused_without_measurement(ctx, nsweeps):
+    # no EM: the launches store no band sums and add none up; the spins are
+    # those of the oracle
+    shape = (256, 132)
+    gs, _ = _gpu_run(ctx, shape, 0.4406868, 31, nsweeps, 5, 2, 1, (8, 3, 256), measure=False)
+    os_, _ = _oracle_run(shape, 0.4406868, 31, nsweeps, 5, 2, 1)
+    assert np.array_equal(gs, os_)
 
 
 def test_fused_tie_queue_overflow(ctx):
