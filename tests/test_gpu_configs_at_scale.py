@@ -38,13 +38,15 @@ def ctx():
     return mcs.Context(0)
 
 
-def test_headline_call_3x4096_betas_tuned_plan(ctx):
+@pytest.mark.parametrize("plan", [(16, 2, 512), (16, 4, 512)])
+def test_headline_call_3x4096_betas_tuned_plan(ctx, plan):
+    # the benchmark's launch shape (16, 2, 512) and the earlier (16, 4, 512)
     L, betas, seed, nsw, sweep0 = 4096, [0.40, BETA_C, 0.50], 7, 12, 100
     g = mcs.make_geom(2, L, count=3)
     lat = mcs.lattice_tensor(g)
     ctx.init(g, lat, mcs.HOT, seed, 0)
     ws = torch.empty(ctx.sweep_workspace_bytes(g), dtype=torch.uint8, device="cuda")
-    ctx.set_tile_plan(g, 16, 4, 512)
+    ctx.set_tile_plan(g, *plan)
     EM = torch.empty((nsw, 3, 2), dtype=torch.int64, device="cuda")
     ctx.sweep_betas(g, lat, betas, seed, nsw, sweep0=sweep0, replica0=0, EM=EM, ws=ws)
     torch.cuda.synchronize()
