@@ -121,10 +121,11 @@ int mc_couplings(mc_ctx *ctx, const mc_geom *geom, int8_t *J, uint64_t seed, voi
 /* Bytes of scratch mc_sweep can use to run several sweeps per fused launch:
  * two bit-packed copies of the lattices (count * Lz * Ly * Lx / 8 bytes
  * each), between which the launches of one call ping-pong; in 3D the
- * couplings packed once per call (3 * Lz * Ly * Lx / 8 bytes); then two
- * arrays of per-tile (E, M) sums of one launch, each rounded up to a multiple
- * of 256 bytes: 8 * count * ceil(Ly / 4) * 16 bytes in 2D, 4 * count *
- * ceil(Ly / 4) * ceil(Lz / 4) * 16 in 3D.  Only the first launch reads and
+ * couplings packed once per call (3 * Lz * Ly * Lx / 8 bytes), the total so
+ * far rounded up to a multiple of 256; then two arrays of per-tile (E, M)
+ * sums of one launch, each rounded up to a multiple of 256 bytes: 8 * count *
+ * ceil(Ly / 4) * 16 bytes in 2D, 4 * count * ceil(Ly / 4) * ceil(Lz / 4) * 16
+ * in 3D.  Only the first launch reads and
  * only the last writes the caller's int8 lattices.  Non-zero
  * for int8 geometries with Lx a multiple of 64: 2D with Lx <= 16384, 3D with
  * Lx <= 4096 and Ly, Lz >= 4.  With a smaller or NULL workspace mc_sweep uses

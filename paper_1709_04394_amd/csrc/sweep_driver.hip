@@ -23,18 +23,23 @@ static bool fused3d_geom(const Geom &g, int layout)
     return layout == MC_INT8 && g.dims == 3 && g.Lx % 64 == 0 && g.Lx <= 4096 && g.Ly >= 4 && g.Lz >= 4;
 }
 
-// Two packed copies (ping-pong between the launches of one call), two
-// arrays of per-tile (E, M) sums (ping-pong likewise) and, in 3D, the
-// couplings in packed form (three directions), whether or not a call has
-// couplings.
+// Two packed copies (ping-pong between the launches of one call), in 3D the
+// couplings in packed form (three directions, whether or not a call has
+// couplings), then two arrays of per-tile (E, M) sums (ping-pong likewise).
+// The 2D packed copies end on a multiple of 16 bytes (Lx / 4 bytes per row
+// pair); in 3D the slots start on the next multiple of 256.
+static size_t fused_slots_offset(const Geom &g)
+{
+    if (g.dims == 2) return 2 * packed_bytes(g);
+    Geom one = g;
+    one.count = 1;
+    return (2 * packed_bytes(g) + 3 * packed_bytes(one) + 255) & ~(size_t)255;
+}
+
 size_t fused_workspace_bytes(const Geom &g, int layout)
 {
-    if (fused2d_geom(g, layout)) return 2 * packed_bytes(g) + 2 * tile2d_slot_bytes(g);
-    if (fused3d_geom(g, layout)) {
-        Geom one = g;
-        one.count = 1;
-        return 2 * packed_bytes(g) + 3 * packed_bytes(one) + 2 * tile3d_slot_bytes(g);
-    }
+    if (fused2d_geom(g, layout)) return fused_slots_offset(g) + 2 * tile2d_slot_bytes(g);
+    if (fused3d_geom(g, layout)) return fused_slots_offset(g) + 2 * tile3d_slot_bytes(g);
     return 0;
 }
 
@@ -121,19 +126,14 @@ static int run_fused(mc_ctx *ctx, const SweepCall &c, const TilePlan &p, int8_t 
     const bool three = c.g.dims == 3;
     const std::vector<int> sizes = split_launches(nsweeps, p.K);
     char *pk[2] = {ws, ws + packed_bytes(c.g)};
-    char *after = ws + 2 * packed_bytes(c.g);
     uint32_t *Jp = nullptr;
-    if (three) {
-        Geom one = c.g;
-        one.count = 1;
-        if (c.J) {
-            Jp = (uint32_t *)after;
-            e = launch_pack_couplings(c.g, c.J, Jp, s);
-        }
-        after += 3 * packed_bytes(one);
+    if (three && c.J) {
+        Jp = (uint32_t *)(ws + 2 * packed_bytes(c.g));
+        e = launch_pack_couplings(c.g, c.J, Jp, s);
     }
+    char *slots = ws + fused_slots_offset(c.g);
     const size_t slot_bytes = three ? tile3d_slot_bytes(c.g) : tile2d_slot_bytes(c.g);
-    int64_t *slot[2] = {(int64_t *)after, (int64_t *)(after + slot_bytes)};
+    int64_t *slot[2] = {(int64_t *)slots, (int64_t *)(slots + slot_bytes)};
     int tiles;
     if (three) {
         tiles = ((c.g.Ly + p.H - 1) / p.H) * ((c.g.Lz + p.H - 1) / p.H);

@@ -223,6 +223,7 @@ def test_tile_plans_default_set_and_limits(ctx):
     (2, (4096, 4096), mcs.INT8, 3), (3, (256, 256, 256), mcs.INT8, 1), (2, (128, 64), mcs.INT8, 1),
     (2, (16384, 8), mcs.INT8, 1), (3, (64, 4, 8), mcs.INT8, 2), (3, (4096, 4, 4), mcs.INT8, 1),
     (2, (96, 96), mcs.INT8, 1), (2, (4096, 4096), mcs.MSC64, 1), (3, (8192, 8, 8), mcs.INT8, 1),
+    (3, (64, 6, 10), mcs.INT8, 1),
     (2, (32768, 4), mcs.INT8, 1), (3, (64, 2, 8), mcs.INT8, 1)])
 def test_sweep_workspace_bytes_follow_the_header(dims, L, layout, count):
     """Two packed copies of the lattices (count N / 8 bytes each), in 3D three
@@ -237,7 +238,8 @@ def test_sweep_workspace_bytes_follow_the_header(dims, L, layout, count):
         L[0] <= 16384 if dims == 2 else (L[0] <= 4096 and min(L[1], L[2]) >= 4))
     up = lambda b: -(-b // 256) * 256
     slots = up(4 * count * -(-L[1] // 4) * -(-L[2] // 4) * 16) if dims == 3 else up(8 * count * -(-L[1] // 4) * 16)
-    expect = (2 * count * N // 8 + (3 * N // 8 if dims == 3 else 0) + 2 * slots) if fused else 0
+    head = up(2 * count * N // 8 + 3 * N // 8) if dims == 3 else 2 * count * N // 8  # slots 256-aligned in 3D
+    expect = (head + 2 * slots) if fused else 0
     assert mcs._lib.mc_sweep_workspace_bytes(ctypes.byref(g)) == expect
 
 
