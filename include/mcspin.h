@@ -124,7 +124,7 @@ int mc_couplings(mc_ctx *ctx, const mc_geom *geom, int8_t *J, uint64_t seed, voi
  * couplings packed once per call (3 * Lz * Ly * Lx / 8 bytes), the total so
  * far rounded up to a multiple of 256; then two arrays of per-tile (E, M)
  * sums of one launch, each rounded up to a multiple of 256 bytes: 8 * count *
- * ceil(Ly / 4) * 16 bytes in 2D, 4 * count * ceil(Ly / 4) * ceil(Lz / 4) * 16
+ * ceil(Ly / 4) * 16 bytes in 2D, 4 * count * ceil(Ly / 2) * ceil(Lz / 2) * 16
  * in 3D.  Only the first launch reads and
  * only the last writes the caller's int8 lattices.  Non-zero
  * for int8 geometries with Lx a multiple of 64: 2D with Lx <= 16384, 3D with
@@ -262,7 +262,7 @@ int mc_sweep_path(mc_ctx *ctx, const mc_geom *geom, int32_t rule, int32_t has_co
  * default).  Host-only calls.  A plan needs H >= 1, K >= 1 and threads a
  * multiple of 64 in 64..1024; in 2D H >= 4, K <= 8, the Lx/64 words of a row either
  * at most threads or a multiple of it, and (H + 4K) rows of 2 Lx/64 words
- * in at most 64 KB of LDS; in 3D H >= 4, K <= 4, Lx/64 <= threads, H <= min(Ly, Lz)
+ * in at most 64 KB of LDS; in 3D H >= 2, K <= 4, Lx/64 <= threads, H <= min(Ly, Lz)
  * and the tile with its couplings in at most 96 KB.  MC_E_RANGE otherwise,
  * the geometry's own errors as for mc_sweep.                               */
 int mc_set_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t H, int32_t K, int32_t threads);

@@ -502,10 +502,11 @@ hipError_t launch_tile3d(const SweepCall &c, const void *src, int in_packed, voi
 }
 
 // Per-tile (E, M) slots of one launch: K <= 4 sweeps x count lattices x
-// ceil(Ly / 4) ceil(Lz / 4) tiles (a plan's tile side is at least 4) x 16 bytes.
+// ceil(Ly / 2) ceil(Lz / 2) tiles (a plan's tile side is at least 2, the
+// smallest that fits LDS at Lx = 4096) x 16 bytes.
 size_t tile3d_slot_bytes(const Geom &g)
 {
-    const size_t b = (size_t)4 * (size_t)g.count * (size_t)((g.Ly + 3) / 4) * (size_t)((g.Lz + 3) / 4) * 16;
+    const size_t b = (size_t)4 * (size_t)g.count * (size_t)((g.Ly + 1) / 2) * (size_t)((g.Lz + 1) / 2) * 16;
     return (b + 255) / 256 * 256;
 }
 

@@ -196,14 +196,17 @@ def test_tile_plans_default_set_and_limits(ctx):
     """Launch shapes of the fused sweeps (host logic only): the built-in plans,
     set/get per geometry, and the limits a plan must meet (threads a multiple
     of 64 up to 1024; 2D: H >= 4, K <= 8, (H + 4K) rows x 2 Lx/64 words of LDS <= 64 KB;
-    3D: H >= 4, K <= 4, H <= min(Ly, Lz), the tile with couplings <= 96 KB)."""
+    3D: H >= 2, K <= 4, H <= min(Ly, Lz), the tile with couplings <= 96 KB)."""
     g2 = mcs.make_geom(2, 4096, count=3)
     g3 = mcs.make_geom(3, 256)
     # 2D: 256 bands over the three lattices -> H = 4096 // 85 = 48, two sweeps
     # per launch, (48 + 4) rows x 64 words of tasks -> 1024 threads
     assert _plan(ctx, g2) == (48, 2, 1024)
-    # 3D: 16 x 16 tiles (one per CU at 256^3), two sweeps, 1024 threads
-    assert _plan(ctx, g3) == (16, 2, 1024)
+    # 3D: 16 x 16 tiles (one per CU at 256^3), two sweeps, 768 threads; 256
+    # threads with four tiles per CU
+    assert _plan(ctx, g3) == (16, 2, 768)
+    assert _plan(ctx, mcs.make_geom(3, 256, count=4)) == (16, 2, 256)
+    assert _plan(ctx, mcs.make_geom(3, 256, count=2)) == (16, 2, 512)
     set_ = lambda g, H, K, T: mcs._lib.mc_set_tile_plan(ctx, ctypes.byref(g), H, K, T)
     assert set_(g2, 16, 4, 512) == 0
     assert _plan(ctx, g2) == (16, 4, 512)
@@ -212,7 +215,7 @@ def test_tile_plans_default_set_and_limits(ctx):
                     (3, 1, 512), (200, 8, 1024)]:  # the last: (200 + 32) x 128 words x 4 B = 116 KB of LDS
         assert set_(g2, H, K, T) == mcs.MC_E_RANGE, (H, K, T)
     assert _plan(ctx, g2) == (16, 4, 512)  # a rejected plan leaves the set one
-    for H, K, T in [(16, 5, 1024), (257, 1, 1024), (3, 1, 256), (32, 4, 1024)]:  # the last: 48^2 x 8 words x 4 B > 96 KB
+    for H, K, T in [(16, 5, 1024), (257, 1, 1024), (1, 1, 256), (32, 4, 1024)]:  # the last: 48^2 x 8 words x 4 B > 96 KB
         assert set_(g3, H, K, T) == mcs.MC_E_RANGE, (H, K, T)
     assert set_(g3, 8, 4, 256) == 0 and _plan(ctx, g3) == (8, 4, 256)
     bad = mcs.Geom(2, 5, 8, 1, mcs.INT8, 1)
@@ -229,7 +232,7 @@ def test_sweep_workspace_bytes_follow_the_header(dims, L, layout, count):
     """Two packed copies of the lattices (count N / 8 bytes each), in 3D three
     packed coupling planes (N / 8 each), then two arrays of per-tile (E, M)
     sums, each rounded up to 256 bytes (2D: 8 sweeps x count x ceil(Ly / 4)
-    bands x 16 bytes; 3D: 4 sweeps x count x ceil(Ly / 4) ceil(Lz / 4) tiles
+    bands x 16 bytes; 3D: 4 sweeps x count x ceil(Ly / 2) ceil(Lz / 2) tiles
     x 16 bytes); zero where no fused kernel applies (MSC64, Lx not a multiple
     of 64, 2D Lx > 16384, 3D Lx > 4096 or Ly, Lz < 4)."""
     g = mcs.make_geom(dims, L, layout=layout, count=count)
@@ -237,7 +240,7 @@ def test_sweep_workspace_bytes_follow_the_header(dims, L, layout, count):
     fused = layout == mcs.INT8 and L[0] % 64 == 0 and (
         L[0] <= 16384 if dims == 2 else (L[0] <= 4096 and min(L[1], L[2]) >= 4))
     up = lambda b: -(-b // 256) * 256
-    slots = up(4 * count * -(-L[1] // 4) * -(-L[2] // 4) * 16) if dims == 3 else up(8 * count * -(-L[1] // 4) * 16)
+    slots = up(4 * count * -(-L[1] // 2) * -(-L[2] // 2) * 16) if dims == 3 else up(8 * count * -(-L[1] // 4) * 16)
     head = up(2 * count * N // 8 + 3 * N // 8) if dims == 3 else 2 * count * N // 8  # slots 256-aligned in 3D
     expect = (head + 2 * slots) if fused else 0
     assert mcs._lib.mc_sweep_workspace_bytes(ctypes.byref(g)) == expect
