@@ -55,7 +55,8 @@ def _run(ctx, shape, rule, beta, seed, nsweeps, plan=None, count=1, replica0=0, 
 @pytest.mark.parametrize("shape,plan", [((64, 8, 8), (4, 1, 64)), ((64, 8, 8), (8, 2, 128)), ((64, 12, 10), (5, 3, 256)),
                                         ((128, 6, 10), (4, 4, 512)), ((64, 16, 16), (16, 1, 1024)),
                                         ((192, 6, 10), (4, 2, 64)), ((64, 20, 12), None),
-                                        ((64, 4, 4), (4, 3, 64)), ((64, 64, 64), (4, 1, 64))])
+                                        ((64, 4, 4), (4, 3, 64)), ((64, 64, 64), (4, 1, 64)),
+                                        ((64, 6, 10), (2, 1, 64)), ((128, 6, 10), (3, 2, 128))])
 @pytest.mark.parametrize("nsweeps", [1, 4, 9])
 def test_fused3d_matches_oracle(ctx, rule, shape, plan, nsweeps):
     _run(ctx, shape, rule, 0.2216546, 11, nsweeps, plan=plan, count=2, replica0=3, sweep0=(1 << 32) - 3)
