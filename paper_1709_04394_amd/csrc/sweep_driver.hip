@@ -84,7 +84,8 @@ TilePlan default_tile_plan(const Geom &g)
 // the workgroup every thread must take the same number of words, because the
 // tie queue's fill level is kept wave-uniform by all lanes taking part in the
 // same ballots.  3D tiles are H x H rows (y, z); their LDS (with room for
-// couplings) must fit in 96 KB.
+// couplings) must fit in 96 KB.  The band height (2D) or tile side (3D) has a
+// floor, 4 or 2, for which the workspace's per-tile (E, M) slots are sized.
 static bool plan_ok(const Geom &g, const TilePlan &p)
 {
     const int Wd = g.Lx / 64;
