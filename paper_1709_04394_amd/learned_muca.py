@@ -196,6 +196,31 @@ def arm_summary(r):
             "seconds": round(float(r["seconds"]), 2), "final_min_over_max": float(r["min_over_max"])}
 
 
+def score_markdown(out):
+    """The score stage's summed runs as markdown: per arm and seed the error
+    after each checkpoint of the accumulated production, and where the
+    target was first met."""
+    t = out["target"]
+    lines = []
+    for arm in ("plain", "learned"):
+        for sd, v in out["arms"][arm]["summed_production"].items():
+            lines += ["## %s arm (weights of seed %s; runs %s)" % (arm, sd, ", ".join(v["runs"])), "",
+                      "| Production walker-sweeps | Error (log-sum-exp) | Error (best constant) |", "|---|---|---|"]
+            lines += ["| %.3g | %.4f | %.4f |" % (c["walker_sweeps"], c["error_logsumexp"], c["error_best_constant"])
+                      for c in v["curve"]]
+            lines.append("")
+            fl, hit = v["flat_walker_sweeps"], v["production_walker_sweeps_to_target"]
+            if hit:
+                lines.append("Within %g after %.3g production walker-sweeps; with the %.3g walker-sweeps of the flat "
+                             "phase, %.3g in total." % (t, hit, fl, fl + hit))
+            else:
+                last = v["curve"][-1]
+                lines.append("Not within %g after %.3g production walker-sweeps (last error %.4f); flat phase %.3g "
+                             "walker-sweeps." % (t, last["walker_sweeps"], last["error_logsumexp"], fl))
+            lines.append("")
+    return "\n".join(lines)
+
+
 def main(argv=None):
     """Stages of the learned-vs-plain comparison at one size:
       converge --L L --seeds S,.. --out DIR
@@ -208,14 +233,15 @@ def main(argv=None):
             production at the arm's converged weights of seed S (walker seed
             P): cumulative histograms after C1 .. Cn sweeps,
             DIR/prod_<arm>_<S>_<P>.npy
-      score --dir DIR --exact FILE [--target 0.01]
+      score --dir DIR --exact FILE [--target 0.01] [--markdown]
             max |ln g error| of every production checkpoint, after matching
             the normalisations by log-sum-exp over the window levels with
             states (the accuracy metric) and after the best constant; the
             walker-sweeps at the first checkpoint within the target; the
             same for the runs at one seed's weights added together, with
             the flat phase's walker-sweeps; sweeps to flat per arm over the
-            seeds"""
+            seeds.  JSON, or with --markdown one table per arm and seed of
+            the runs added together"""
     import argparse
     import glob
     import json
@@ -239,6 +265,7 @@ def main(argv=None):
     s.add_argument("--dir", required=True)
     s.add_argument("--exact", required=True, help="stored exact ln g over the window levels (text)")
     s.add_argument("--target", type=float, default=0.01)
+    s.add_argument("--markdown", action="store_true", help="tables of the summed runs instead of JSON")
     a = p.parse_args(argv)
 
     if a.stage == "score":
@@ -294,7 +321,7 @@ def main(argv=None):
             out["arms"][arm] = row
         pl, le = out["arms"]["plain"]["mean"], out["arms"]["learned"]["mean"]
         out["mean_sweeps_to_flat_ratio_learned_over_plain"] = le / pl
-        print(json.dumps(out, indent=1))
+        print(score_markdown(out) if a.markdown else json.dumps(out, indent=1))
         return
 
     from . import Context

@@ -81,3 +81,13 @@ def test_score_stage_end_to_end(tmp_path, capsys):
     assert max(pp["errors_best_constant"]) < 1e-9 and pp["walker_sweeps_to_target"] == 10 * 64
     assert abs(lp["errors_best_constant"][0] - np.log(2) / 2) < 1e-9
     assert lp["errors_best_constant"][1] > 1e-3 and lp["walker_sweeps_to_target"] is None
+    # the same files as markdown: one table per arm and seed of the summed runs
+    lm.main(["score", "--dir", str(tmp_path), "--exact", GOLD, "--target", "0.01", "--markdown"])
+    md = capsys.readouterr().out
+    assert "## plain arm (weights of seed 1; runs prod_plain_1_7)" in md
+    assert "## learned arm (weights of seed 1; runs prod_learned_1_7)" in md
+    assert md.count("| Production walker-sweeps |") == 2 and md.count("\n| 640 |") == 2
+    # plain: within the target at the first checkpoint, 10 sweeps x 64 walkers
+    # of production plus 900 x 4096 of the flat phase
+    assert "Within 0.01 after 640 production walker-sweeps; with the 3.69e+06 walker-sweeps of the flat" in md
+    assert "Not within 0.01 after 1.92e+03 production walker-sweeps" in md
