@@ -269,10 +269,12 @@ int mc_set_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t H, int32_t K, int
 int mc_get_tile_plan(mc_ctx *ctx, const mc_geom *geom, int32_t *H, int32_t *K, int32_t *threads);
 
 /* Autotuner: times every admissible (H, K, threads) for this geometry with
- * `sweeps` measured sweeps (per-sweep E, M, as mc_sweep with EM) at inverse
- * temperature beta, in the steady state of a long call (packed rows in and
- * out), on two caller-provided scratch lattices (device, count * N bytes
- * each; overwritten), and keeps the fastest shape on the context.
+ * `sweeps` measured sweeps (the launches that compute per-sweep E, M, as
+ * mc_sweep with EM; their per-tile sums go to the second half of scratch_b
+ * and are not added up) at inverse temperature beta, in the steady state of
+ * a long call (packed rows in and out), on two caller-provided scratch
+ * lattices (device, count * N bytes each; overwritten), and keeps the
+ * fastest shape on the context.
  * Synchronises the stream.                                                 */
 int mc_tune_sweep(mc_ctx *ctx, const mc_geom *geom, void *scratch_a, void *scratch_b, double beta,
                   int32_t sweeps, void *stream);
